@@ -1,0 +1,193 @@
+/*
+ * peel.h -- C ABI of libpeel, round-synchronous parallel peeling on gfx950.
+ *
+ * Paper: J. Jiang, M. Mitzenmacher, J. Thaler, "Parallel Peeling Algorithms".
+ *
+ * Two forms of one process.  (1) k-core peeling of an r-uniform hypergraph:
+ * in each round every vertex of degree < k is removed at once together with
+ * its incident edges, until no vertex of degree < k is left (Section 1;
+ * Section 3).  (2) Listing an Invertible Bloom Lookup Table: keys are edges,
+ * cells are vertices, and in each round every pure cell gives up its key,
+ * which is then deleted from its r cells (Section 5).  No edge or key is ever
+ * peeled twice (Section 5, "Implementation Details").
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers marked (device) are device memory of the current HIP device;
+ *     pointers marked (host) are host memory read before the call returns.
+ *   - The caller owns every buffer.  The library never allocates, frees or
+ *     copies to the host; scratch space is the caller's workspace, sized by
+ *     the matching *_workspace() query, 256-byte aligned.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work on it and return without waiting.  The returned status covers
+ *     argument errors found on the host, and launch failures.  Errors found
+ *     by the device (an id out of range, a round limit, a corrupt cell) are
+ *     written as flags into the call's device summary, to be read after the
+ *     stream is synchronised.
+ *   - Rounds are numbered from 1.  Round numbers stored per vertex or edge
+ *     use 0 for "still present at the end" (in the k-core / in the table).
+ *   - Calls on different streams are independent when their buffers and
+ *     workspaces are disjoint.
+ */
+#ifndef PEEL_H
+#define PEEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t peel_status;
+
+#define PEEL_OK 0
+#define PEEL_EINVAL (-1)   /* bad argument (size, null pointer, r, k)        */
+#define PEEL_ERANGE (-2)   /* a vertex id >= n                               */
+#define PEEL_ENOSPC (-3)   /* output or workspace too small                  */
+#define PEEL_EROUNDS (-4)  /* round limit reached before the process ended   */
+#define PEEL_ECORRUPT (-5) /* an IBLT cell with count 1 and a bad checksum   */
+#define PEEL_EHIP (-6)     /* the HIP runtime reported an error              */
+
+/* Device summary flag bits (summary status words). */
+#define PEEL_FLAG_ERANGE 0x1u
+#define PEEL_FLAG_EROUNDS 0x2u
+#define PEEL_FLAG_ENOSPC 0x4u
+#define PEEL_FLAG_ECORRUPT 0x8u
+#define PEEL_FLAG_TIMEOUT 0x10u /* a device-wide barrier waited past its limit */
+
+/* Human-readable name of a status code; never NULL. */
+const char *peel_strerror(peel_status s);
+
+/* ABI revision of this header; bumped on any incompatible change. */
+int peel_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Hypergraph incidence (CSR).                                              */
+/*
+ * The peeling process removes a vertex "together with its incident edges"
+ * (Section 1), so peel_kcore needs, per vertex, the list of edges that hold
+ * it.  hg_build makes it by counting sort.
+ *
+ *   edges   (device) m rows of r uint32 vertex ids, row-major (edge e holds
+ *           edges[e*r .. e*r+r-1]).  An id may repeat inside a row; degree
+ *           then counts it with multiplicity.
+ *   m, r, n 2 <= r <= 8, n >= 1, m*r < 2^32.
+ *   offsets (device, out) n+1 uint32: the incidences of vertex v are
+ *           inc[offsets[v] .. offsets[v+1]-1]; offsets[n] = m*r.
+ *   inc     (device, out) m*r uint32 edge ids.  Order within a vertex's list
+ *           is unspecified.
+ *   deg     (device, out) n uint32: offsets[v+1] - offsets[v].
+ *   info    (device, out) 2 uint32: [0] status flags (PEEL_FLAG_ERANGE if an
+ *           id >= n was seen; the other outputs are then undefined),
+ *           [1] maximum degree.
+ *   ws      (device) workspace of ws_bytes >= hg_build_workspace(n, m, r).
+ */
+size_t hg_build_workspace(uint32_t n, uint64_t m, uint32_t r);
+peel_status hg_build(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n,
+                     uint32_t *offsets, uint32_t *inc, uint32_t *deg, uint32_t *info,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Round-synchronous k-core peeling (Section 1; Section 3; Section 5).      */
+/*
+ * Round t removes F_t = { alive v : deg(v) < k }, degrees taken at the start
+ * of round t, and every alive edge that holds a vertex of F_t; each removed
+ * edge lowers the degree of each of its r slots by one.  The run stops at the
+ * first empty F_t.  An edge hit by several peeled vertices in one round dies
+ * once (it is claimed by compare-and-swap on its round word).
+ *
+ *   edges, m, r, n   as for hg_build;  k >= 1.
+ *   offsets, inc     (device) the CSR from hg_build for these edges.
+ *   deg              (device, in/out) n uint32.  In: the degrees from
+ *                    hg_build.  Out: the core degree of each core vertex, 0
+ *                    for every removed vertex.
+ *   vertex_round     (device, out) n uint32: round that removed v, 0 = core.
+ *   edge_round       (device, out) m uint32: round that removed e, 0 = core.
+ *   round_stats      (device, out) 2*max_rounds uint64: for round t,
+ *                    [2(t-1)] = vertices removed, [2(t-1)+1] = edges removed.
+ *                    Entries past the last round are 0.
+ *   max_rounds       >= 1.  If round max_rounds+1 would still remove a vertex,
+ *                    the run stops and sets PEEL_FLAG_EROUNDS; the outputs
+ *                    then hold the state after max_rounds rounds.
+ *   summary          (device, out) 4 uint32: [0] rounds (last round that
+ *                    removed a vertex), [1] last round that removed an edge,
+ *                    [2] status flags, [3] number of core vertices.
+ *   ws               (device) ws_bytes >= peel_kcore_workspace(n, m, r).
+ */
+size_t peel_kcore_workspace(uint32_t n, uint64_t m, uint32_t r);
+peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n, uint32_t k,
+                       const uint32_t *offsets, const uint32_t *inc, uint32_t *deg,
+                       uint32_t *vertex_round, uint32_t *edge_round, uint64_t *round_stats,
+                       uint32_t max_rounds, uint32_t *summary, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Invertible Bloom Lookup Table (Section 5).                                */
+/*
+ * A table of `ncells` cells split into r near-equal subtables (subtable j
+ * holds ncells/r cells, the first ncells%r subtables one more); a key has one
+ * cell in each subtable (Section 5, "Implementation Details"; Appendix B).
+ * Cell of key x in subtable j: base_j + floor(H_j(x) * size_j / 2^64) with
+ * H_j(x) = mix64(x ^ salt_j); checksum C(x) = mix64(x ^ salt_c); mix64 is the
+ * SplitMix64 output finaliser and salt_j (j < r), salt_c are draws j and 8 of
+ * the SplitMix64 stream whose state starts at `seed`.
+ *
+ * A cell is pure when count == 1 and hash_sum == C(key_sum): it holds exactly
+ * one key, key_sum.
+ */
+typedef struct iblt_cell {
+    int32_t count;      /* keys inserted minus keys deleted */
+    uint32_t reserved0; /* 0 */
+    uint64_t key_sum;   /* XOR of the keys                  */
+    uint64_t hash_sum;  /* XOR of C(key)                    */
+    uint64_t reserved1; /* 0; pads the cell to 32 bytes     */
+} iblt_cell;
+
+typedef struct iblt_desc {
+    uint64_t ncells; /* r <= ncells < 2^32 */
+    uint32_t r;      /* 2..8 */
+    uint32_t reserved;
+    uint64_t seed;
+} iblt_desc;
+
+/*
+ * Insert keys: for each key x and each subtable j, count += 1,
+ * key_sum ^= x, hash_sum ^= C(x) in x's cell of subtable j (Section 5,
+ * "Motivation").  Accumulates into `cells` (device, ncells entries), which
+ * the caller zeroes before the first insert.  Keys (device) must be
+ * distinct from each other and from keys already in the table: a repeated
+ * key cancels in the XOR fields.
+ */
+peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
+                        uint64_t nkeys, void *stream);
+
+/*
+ * List the table by round-synchronous pure-cell peeling, consuming `cells`
+ * in place.  Round t takes K_t = the keys of the cells that are pure at the
+ * start of the round (each key once, however many of its cells are pure);
+ * the run stops at the first empty K_t; every key of K_t is then deleted
+ * from its r cells.
+ *
+ *   out_keys     (device, out) keys, grouped by round in round order; the
+ *                order inside a round is unspecified.
+ *   out_cap      capacity of out_keys.  If a round would overflow it, the run
+ *                stops before that round and sets PEEL_FLAG_ENOSPC.
+ *   round_stats  (device, out) max_rounds uint64: K_t per round.
+ *   max_rounds   >= 1; PEEL_FLAG_EROUNDS as for peel_kcore.
+ *   summary      (device, out) 4 uint64: [0] keys listed, [1] rounds, [2]
+ *                keys still in the table (sum of counts / r minus [0]; 0 means
+ *                the table was emptied), [3] status flags (PEEL_FLAG_ECORRUPT
+ *                if a count-1 cell failed its checksum; such a cell is not
+ *                pure).
+ *   ws           (device) ws_bytes >= iblt_list_workspace(desc).
+ */
+size_t iblt_list_workspace(const iblt_desc *desc);
+peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
+                      uint64_t out_cap, uint64_t *round_stats, uint32_t max_rounds,
+                      uint64_t *summary, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEEL_H */

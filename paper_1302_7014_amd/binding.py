@@ -1,0 +1,203 @@
+"""Thin ctypes binding of ``libpeel.so`` (the C ABI in ``include/peel.h``).
+
+Argument marshalling only: every step of the path runs in the HIP kernels.
+PyTorch supplies device memory and the current stream.  Unsigned 32-bit and
+64-bit device arrays travel as ``torch.int32`` / ``torch.int64`` tensors of the
+same bit patterns; an IBLT table is an ``(ncells, 4)`` ``torch.int64`` tensor,
+32 bytes per cell laid out as ``iblt_cell`` (count in the low half of column
+0, key_sum in column 1, hash_sum in column 2).
+
+There is no fallback: if the library is not built, or no GPU is present, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpeel.so")
+
+PEEL_OK, PEEL_EINVAL, PEEL_ERANGE, PEEL_ENOSPC, PEEL_EROUNDS, PEEL_ECORRUPT, PEEL_EHIP = (
+    0, -1, -2, -3, -4, -5, -6)
+FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT = 0x1, 0x2, 0x4, 0x8, 0x10
+
+# Every symbol include/peel.h declares.
+EXPORTS = ("peel_strerror", "peel_abi_version", "hg_build_workspace", "hg_build",
+           "peel_kcore_workspace", "peel_kcore", "iblt_insert", "iblt_list_workspace", "iblt_list")
+
+_lib = None
+
+
+class PeelError(RuntimeError):
+    pass
+
+
+class IbltDesc(C.Structure):
+    _fields_ = [("ncells", C.c_uint64), ("r", C.c_uint32), ("reserved", C.c_uint32),
+                ("seed", C.c_uint64)]
+
+
+def lib() -> C.CDLL:
+    """Load libpeel.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PeelError(f"{LIB_PATH} is not built: run `python -m paper_1302_7014_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, u32, u64, sz = C.c_void_p, C.c_uint32, C.c_uint64, C.c_size_t
+        L.peel_strerror.argtypes = [C.c_int32]
+        L.peel_strerror.restype = C.c_char_p
+        L.peel_abi_version.restype = C.c_int
+        L.hg_build_workspace.argtypes = [u32, u64, u32]
+        L.hg_build_workspace.restype = sz
+        L.hg_build.argtypes = [P, u64, u32, u32, P, P, P, P, P, sz, P]
+        L.peel_kcore_workspace.argtypes = [u32, u64, u32]
+        L.peel_kcore_workspace.restype = sz
+        L.peel_kcore.argtypes = [P, u64, u32, u32, u32, P, P, P, P, P, P, u32, P, P, sz, P]
+        L.iblt_insert.argtypes = [C.POINTER(IbltDesc), P, P, u64, P]
+        L.iblt_list_workspace.argtypes = [C.POINTER(IbltDesc)]
+        L.iblt_list_workspace.restype = sz
+        L.iblt_list.argtypes = [C.POINTER(IbltDesc), P, P, u64, P, u32, P, P, sz, P]
+        for f in ("hg_build", "peel_kcore", "iblt_insert", "iblt_list"):
+            getattr(L, f).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(st: int, what: str) -> None:
+    if st != PEEL_OK:
+        raise PeelError(f"{what}: {lib().peel_strerror(st).decode()} ({st})")
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise PeelError("device tensor expected")
+    if not t.is_contiguous():
+        raise PeelError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _empty(n: int, dtype, device) -> torch.Tensor:
+    return torch.empty(max(int(n), 1), dtype=dtype, device=device)
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A device workspace of at least ``nbytes`` (256-byte aligned by the allocator)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+@dataclass
+class Csr:
+    offsets: torch.Tensor  # int32[n+1] (uint32 bits)
+    inc: torch.Tensor      # int32[m*r]
+    deg: torch.Tensor      # int32[n]
+    info: torch.Tensor     # int32[2]: flags, max degree
+
+
+def hg_build_workspace(n: int, m: int, r: int) -> int:
+    return int(lib().hg_build_workspace(n, m, r))
+
+
+def hg_build(edges: torch.Tensor, n: int, out: Csr | None = None, ws: torch.Tensor | None = None,
+             stream=None) -> Csr:
+    """CSR incidence of ``edges`` ((m, r) int32 device tensor of uint32 ids)."""
+    m, r = edges.shape
+    dev = edges.device
+    if out is None:
+        out = Csr(_empty(n + 1, torch.int32, dev), _empty(m * r, torch.int32, dev),
+                  _empty(n, torch.int32, dev), _empty(2, torch.int32, dev))
+    if ws is None:
+        ws = workspace(hg_build_workspace(n, m, r), dev)
+    _check(lib().hg_build(_ptr(edges), m, r, n, _ptr(out.offsets), _ptr(out.inc), _ptr(out.deg),
+                          _ptr(out.info), _ptr(ws), ws.numel(), _stream(stream)), "hg_build")
+    return out
+
+
+@dataclass
+class PeelOut:
+    deg: torch.Tensor           # int32[n]
+    vertex_round: torch.Tensor  # int32[n]
+    edge_round: torch.Tensor    # int32[m]
+    round_stats: torch.Tensor   # int64[2*max_rounds]
+    summary: torch.Tensor       # int32[4]: rounds, edge rounds, flags, core vertices
+
+
+def peel_kcore_workspace(n: int, m: int, r: int) -> int:
+    return int(lib().peel_kcore_workspace(n, m, r))
+
+
+def peel_kcore(edges: torch.Tensor, n: int, k: int, csr: Csr, max_rounds: int = 4096,
+               out: PeelOut | None = None, ws: torch.Tensor | None = None, stream=None) -> PeelOut:
+    """Round-synchronous peel to the k-core; ``csr.deg`` is consumed (see ``out.deg``).
+
+    ``out.deg`` is ``csr.deg`` itself unless ``out`` brings its own degrees
+    (then the caller copies the initial degrees into it).
+    """
+    m, r = edges.shape
+    dev = edges.device
+    if out is None:
+        out = PeelOut(csr.deg, _empty(n, torch.int32, dev), _empty(m, torch.int32, dev),
+                      _empty(2 * max_rounds, torch.int64, dev), _empty(4, torch.int32, dev))
+    if ws is None:
+        ws = workspace(peel_kcore_workspace(n, m, r), dev)
+    _check(lib().peel_kcore(_ptr(edges), m, r, n, k, _ptr(csr.offsets), _ptr(csr.inc),
+                            _ptr(out.deg), _ptr(out.vertex_round), _ptr(out.edge_round),
+                            _ptr(out.round_stats), max_rounds, _ptr(out.summary), _ptr(ws),
+                            ws.numel(), _stream(stream)), "peel_kcore")
+    return out
+
+
+def iblt_desc(ncells: int, r: int, seed: int) -> IbltDesc:
+    return IbltDesc(ncells, r, 0, seed & 0xFFFFFFFFFFFFFFFF)
+
+
+def iblt_table(ncells: int, device) -> torch.Tensor:
+    """A zeroed table: (ncells, 4) int64, one 32-byte iblt_cell per row."""
+    return torch.zeros((ncells, 4), dtype=torch.int64, device=device)
+
+
+def iblt_insert(desc: IbltDesc, cells: torch.Tensor, keys: torch.Tensor, stream=None) -> None:
+    """XOR ``keys`` (int64 device tensor of uint64 keys) into ``cells``."""
+    _check(lib().iblt_insert(C.byref(desc), _ptr(cells), _ptr(keys), keys.numel(),
+                             _stream(stream)), "iblt_insert")
+
+
+@dataclass
+class ListOut:
+    keys: torch.Tensor         # int64[out_cap]
+    round_stats: torch.Tensor  # int64[max_rounds]: keys listed per round
+    summary: torch.Tensor      # int64[4]: listed, rounds, keys left, flags
+
+
+def iblt_list_workspace(desc: IbltDesc) -> int:
+    return int(lib().iblt_list_workspace(C.byref(desc)))
+
+
+def iblt_list(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = None,
+              max_rounds: int = 4096, out: ListOut | None = None, ws: torch.Tensor | None = None,
+              stream=None) -> ListOut:
+    """Round-synchronous listing; consumes ``cells`` in place."""
+    dev = cells.device
+    if out is None:
+        cap = desc.ncells if out_cap is None else out_cap
+        out = ListOut(_empty(cap, torch.int64, dev), _empty(max_rounds, torch.int64, dev),
+                      _empty(4, torch.int64, dev))
+    cap = out.keys.numel() if out_cap is None else out_cap
+    if ws is None:
+        ws = workspace(iblt_list_workspace(desc), dev)
+    _check(lib().iblt_list(C.byref(desc), _ptr(cells), _ptr(out.keys), cap, _ptr(out.round_stats),
+                           max_rounds, _ptr(out.summary), _ptr(ws), ws.numel(), _stream(stream)),
+           "iblt_list")
+    return out

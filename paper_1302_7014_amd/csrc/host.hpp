@@ -1,0 +1,77 @@
+// Host-side helpers for libpeel entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "peel.h"
+
+namespace peel {
+
+#define PEEL_HIP_TRY(expr)                          \
+  do {                                              \
+    hipError_t _e = (expr);                         \
+    if (_e != hipSuccess) return PEEL_EHIP;         \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Carves consecutive 256-byte aligned pieces out of a caller workspace.
+struct Carver {
+  char *base;
+  size_t used = 0;
+  explicit Carver(void *p) : base(static_cast<char *>(p)) {}
+  template <typename T>
+  T *take(size_t count) {
+    T *p = reinterpret_cast<T *>(base + used);
+    used = align_up(used + count * sizeof(T));
+    return p;
+  }
+};
+
+struct DeviceInfo {
+  int id = -1;
+  int cus = 0;
+  uint64_t barrier_limit_ticks = 0;  // ~10 s of the device wall clock
+};
+
+// Properties of the current device (cached per device id).
+inline const DeviceInfo &device_info() {
+  static DeviceInfo cache[64];
+  static std::mutex mu;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  DeviceInfo &d = cache[dev & 63];
+  if (d.id != dev) {
+    int cus = 0, khz = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (khz <= 0) khz = 100000;  // 100 MHz
+    d.cus = cus > 0 ? cus : 1;
+    d.barrier_limit_ticks = (uint64_t)khz * 1000ull * 10ull;
+    d.id = dev;
+  }
+  return d;
+}
+
+// Workgroups of `kernel` (kBlock threads) that fit on the device at once.
+inline int coresident_blocks(const void *kernel, int block, size_t lds_bytes) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds_bytes) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  return per_cu * device_info().cus;
+}
+
+inline unsigned grid_for(uint64_t items, int per_block, unsigned cap = 1u << 20) {
+  uint64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return static_cast<unsigned>(g);
+}
+
+}  // namespace peel

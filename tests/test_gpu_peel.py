@@ -1,0 +1,166 @@
+"""GPU parity of hg_build + peel_kcore against the CPU oracle, bit for bit.
+
+Every comparison is exact: vertex and edge removal rounds, per-round vertex and
+edge counts, round counts, final degrees and the core size.  The CSR is
+compared as per-vertex sorted edge lists (the order inside a list is free).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1302_7014_amd as pk
+
+from oracle import certify, native
+from workloads import configs, gen
+
+from gpu_helpers import dev_u32, gpu_peel, host_u32, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_csr(n, edges, res):
+    m, r = edges.shape
+    deg = np.bincount(edges.ravel().astype(np.int64), minlength=n)
+    assert np.array_equal(res["deg0"], deg)
+    off = host_u32(res["csr"].offsets)[: n + 1].astype(np.int64)
+    assert off[0] == 0 and np.array_equal(np.diff(off), deg)
+    inc = host_u32(res["csr"].inc)[: m * r].astype(np.int64)
+    # each vertex's list is the multiset of edges that hold it
+    want = np.repeat(np.arange(m), r)[np.argsort(edges.ravel(), kind="stable")]
+    got = np.concatenate([np.sort(inc[off[v]:off[v + 1]]) for v in range(n)]) if m else inc
+    assert np.array_equal(got, want)
+    assert res["info"][0] == 0 and res["info"][1] == (deg.max() if n else 0)
+
+
+def _check_against_oracle(n, edges, k, res, max_rounds=1 << 20):
+    o = native.peel_rounds(n, edges, k, max_rounds=max_rounds)
+    assert np.array_equal(res["vertex_round"], o.vertex_round)
+    assert np.array_equal(res["edge_round"], o.edge_round)
+    assert np.array_equal(res["deg"], o.deg)
+    assert np.array_equal(res["V"], o.V) and np.array_equal(res["E"], o.E)
+    assert res["rounds"] == o.rounds and res["edge_rounds"] == o.edge_rounds
+    assert res["core"] == int((o.vertex_round == 0).sum())
+    return o
+
+
+def test_small_hypergraphs_bit_exact():
+    need_gpu()
+    rng = np.random.default_rng(7)
+    for i in range(40):
+        r = int(rng.integers(2, 9))
+        k = int(rng.integers(1, 5))
+        n = int(rng.integers(r, 3000))
+        m = int(rng.integers(0, 3 * n))
+        e = rng.integers(0, n, size=(m, r)).astype(np.uint32)
+        say("small", i, n, m, r, k)
+        res = gpu_peel(n, e, k)
+        assert res["flags"] == 0
+        _check_csr(n, e, res)
+        _check_against_oracle(n, e, k, res)
+
+
+def test_degenerate_inputs():
+    need_gpu()
+    cases = [
+        (1, 2, np.zeros((0, 3), np.uint32)),                       # one vertex, no edges
+        (5, 2, np.zeros((0, 2), np.uint32)),                       # no edges
+        (3, 1, np.array([[0, 1, 2]], np.uint32)),                  # k = 1
+        (3, 2, np.array([[0, 1, 2], [0, 1, 2]], np.uint32)),       # duplicate edge: 2-core
+        (4, 9, np.array([[0, 1, 2, 3]] * 5, np.uint32)),           # k above every degree
+        (7, 2, np.array([[0, 1, 2], [0, 3, 4], [0, 5, 6]], np.uint32)),  # star
+        (2, 2, np.array([[0, 0], [1, 1], [0, 1]], np.uint32)),     # repeated ids in an edge
+        (8, 2, np.array([[j] * 8 for j in range(8)], np.uint32)),  # r = 8, loops
+    ]
+    for n, k, e in cases:
+        say("degenerate", n, k, e.shape)
+        res = gpu_peel(n, e, k)
+        _check_csr(n, e, res)
+        _check_against_oracle(n, e, k, res)
+
+
+def test_config_kcore_small_seeds():
+    need_gpu()
+    spec = configs.kcore_small()
+    for seed in (1, 2, 3, 4, 5):
+        e = spec.edges(seed)
+        say(spec.name, "seed", seed)
+        res = gpu_peel(spec.n, e, spec.k)
+        _check_csr(spec.n, e, res)
+        _check_against_oracle(spec.n, e, spec.k, res)
+
+
+@pytest.mark.parametrize("r,k,c", [(3, 2, 0.9), (4, 2, 0.7), (4, 2, 0.85), (3, 3, 1.4),
+                                   (3, 3, 1.7), (2, 3, 1.2), (5, 2, 0.6), (6, 4, 2.0)])
+def test_medium_models_bit_exact(r, k, c):
+    need_gpu()
+    n = (1 << 18) + 12345  # several tiles and a ragged tail
+    for model in ("partitioned", "gnm"):
+        e = (gen.partitioned_edges if model == "partitioned" else gen.gnm_edges)(n, int(c * n), r, 11)
+        say("medium", model, n, r, k, c)
+        res = gpu_peel(n, e, k)
+        _check_against_oracle(n, e, k, res)
+
+
+def test_round_limit_leaves_consistent_state():
+    need_gpu()
+    n = 1 << 16
+    e = gen.partitioned_edges(n, int(0.7 * n), 4, 5)
+    for cap in (1, 3, 7):
+        say("max_rounds", cap)
+        res = gpu_peel(n, e, 2, max_rounds=cap)
+        o = native.peel_rounds(n, e, 2, max_rounds=cap)
+        assert o.status == native.EROUNDS and res["flags"] & 0x2
+        assert np.array_equal(res["vertex_round"], o.vertex_round)
+        assert np.array_equal(res["edge_round"], o.edge_round)
+        assert np.array_equal(res["deg"], o.deg)
+        assert res["rounds"] == cap
+
+
+def test_out_of_range_ids_flagged():
+    need_gpu()
+    e = np.array([[0, 1, 2], [0, 1, 99]], np.uint32)
+    say("erange")
+    csr = pk.hg_build(dev_u32(e).view(2, 3), 5)
+    torch.cuda.synchronize()
+    info = host_u32(csr.info)
+    assert info[0] & 0x1
+    # the in-range incidences still form a consistent CSR
+    assert host_u32(csr.offsets)[:6].tolist() == [0, 2, 4, 5, 5, 5]
+
+
+def test_repeatable_across_runs():
+    # Outputs are order-independent integers: two runs agree bit for bit.
+    need_gpu()
+    n = 1 << 20
+    e = gen.partitioned_edges(n, int(0.75 * n), 4, 21)
+    say("repeat", n)
+    a = gpu_peel(n, e, 2)
+    b = gpu_peel(n, e, 2)
+    for key in ("vertex_round", "edge_round", "deg", "V", "E"):
+        assert np.array_equal(a[key], b[key])
+
+
+@pytest.mark.parametrize("c", configs.SWEEP_C)
+def test_full_size_sweep_r4_n16M(c):
+    # n = 2^24, r = 4, k = 2: the oracle computes the whole answer on the host.
+    need_gpu()
+    spec = configs.kcore_sweep(c)
+    e = spec.edges(1)
+    say(spec.name)
+    res = gpu_peel(spec.n, e, spec.k)
+    assert res["flags"] == 0
+    _check_against_oracle(spec.n, e, spec.k, res)
+    if c == 0.70:
+        assert certify.peel_certificate(spec.n, e, spec.k, res["vertex_round"], res["edge_round"],
+                                        res["deg"], res["V"], res["E"], res["rounds"],
+                                        res["edge_rounds"]) == []
+
+
+@pytest.mark.parametrize("which", ["lo", "hi"])
+def test_full_size_k3_n4M(which):
+    need_gpu()
+    spec = configs.kcore_k3(which)
+    e = spec.edges(1)
+    say(spec.name)
+    res = gpu_peel(spec.n, e, spec.k)
+    _check_against_oracle(spec.n, e, spec.k, res)
