@@ -1,0 +1,281 @@
+"""Benchmark: round-synchronous k-core peeling at n = 2^24 on one MI355X.
+
+One step = hg_build + peel_kcore over the resident edge list of the r=4, k=2,
+n=2^24, c=0.70 hypergraph (11,744,051 edges, partitioned model, seed 1): the
+whole path from edges in HBM to the k-core, its per-round counts and every
+vertex's and edge's removal round.  `value` is edges peeled per second over
+the step.  The line also carries the roofline of the dominant kernel (HIP
+events on the stream the kernels run on), the CPU oracle timed on the host
+on the same workload, and secondary measurements (peel alone, IBLT insert and
+list at 2^24 cells).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--sweep]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import paper_1302_7014_amd as pk  # noqa: E402
+from workloads import configs, gen  # noqa: E402
+
+METRIC = "edges peeled/sec and HBM GB/s fraction at n=2^24; batched vs plain; p99 decode latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def peel_bytes(n, r, edges, deg0, vr, er):
+    """Algorithmic HBM bytes of one peel: each word read or written once, an atomic
+    or CAS read-modify-write of a w-byte word counts 2w.
+
+    8n (read deg, write vertex_round) + 8 per removed vertex (its offsets pair)
+    + 4 per incidence of a removed vertex (its edge list) + per removed edge
+    8 (claim CAS) + 4r (its row) + 8(r-1) (the other slots' decrements).
+    """
+    removed_v = vr != 0
+    m_rem = int((er != 0).sum())
+    n_rem = int(removed_v.sum())
+    inc_rem = int(deg0[removed_v].astype(np.int64).sum())
+    return 8 * n + 8 * n_rem + 4 * inc_rem + m_rem * (8 + 4 * r + 8 * (r - 1))
+
+
+def build_bytes(n, m, r):
+    """Algorithmic bytes of hg_build: read edges twice (8rm), degree and cursor
+    atomics (16rm), write inc (4rm), scan deg into offsets (8n)."""
+    return 28 * r * m + 8 * n
+
+
+def iblt_insert_bytes(m, r):
+    """Per key: read it (8) and update r cells' count, key and checksum fields (r x 2 x 20)."""
+    return m * (8 + 40 * r)
+
+
+def iblt_list_bytes(N, r, listed):
+    """Round-1 count scan (4N) + per listed key: its pure cell (20), r cell updates
+    (r x 2 x 20) and the output word (8)."""
+    return 4 * N + listed * (20 + 40 * r + 8)
+
+
+class Timer:
+    """Accumulates HIP-event durations of calls made on the current stream."""
+
+    def __init__(self):
+        self.ms = []
+
+    def __enter__(self):
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+        self.a.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record()
+        self._pending = (self.a, self.b)
+        return False
+
+    def collect(self):
+        torch.cuda.synchronize()
+        self.ms.append(self._pending[0].elapsed_time(self._pending[1]))
+
+
+def bench_kcore(spec, steps, warmup):
+    log(f"generating {spec.name}: n={spec.n} m={spec.m} r={spec.r}")
+    e_host = spec.edges(1)
+    dev = torch.device("cuda", 0)
+    e = torch.from_numpy(e_host.view(np.int32)).to(dev)
+    n, m, r = spec.n, spec.m, spec.r
+    csr = pk.Csr(torch.empty(n + 1, dtype=torch.int32, device=dev),
+                 torch.empty(m * r, dtype=torch.int32, device=dev),
+                 torch.empty(n, dtype=torch.int32, device=dev),
+                 torch.empty(2, dtype=torch.int32, device=dev))
+    max_rounds = 4096
+    out = pk.PeelOut(csr.deg, torch.empty(n, dtype=torch.int32, device=dev),
+                     torch.empty(m, dtype=torch.int32, device=dev),
+                     torch.empty(2 * max_rounds, dtype=torch.int64, device=dev),
+                     torch.empty(8, dtype=torch.int32, device=dev))
+    ws_b = pk.workspace(pk.hg_build_workspace(n, m, r), dev)
+    ws_p = pk.workspace(pk.peel_kcore_workspace(n, m, r), dev)
+    tb, tp = Timer(), Timer()
+
+    def step(timed):
+        if timed:
+            with tb:
+                pk.hg_build(e, n, out=csr, ws=ws_b)
+            with tp:
+                pk.peel_kcore(e, n, spec.k, csr, max_rounds=max_rounds, out=out, ws=ws_p)
+        else:
+            pk.hg_build(e, n, out=csr, ws=ws_b)
+            pk.peel_kcore(e, n, spec.k, csr, max_rounds=max_rounds, out=out, ws=ws_p)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    # the degrees right after hg_build, for the byte model
+    pk.hg_build(e, n, out=csr, ws=ws_b)
+    torch.cuda.synchronize()
+    deg0 = csr.deg.cpu().numpy().view(np.uint32).copy()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pk.hg_build(e, n, out=csr, ws=ws_b)
+        pk.peel_kcore(e, n, spec.k, csr, max_rounds=max_rounds, out=out, ws=ws_p)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    # per-call HIP-event durations, measured in separate passes
+    for _ in range(steps):
+        step(True)
+        tb.collect()
+        tp.collect()
+
+    summ = out.summary.cpu().numpy().view(np.uint32)
+    vr = out.vertex_round.cpu().numpy().view(np.uint32)
+    er = out.edge_round.cpu().numpy().view(np.uint32)
+    if int(summ[2]) != 0:
+        raise RuntimeError(f"peel flags {int(summ[2])}")
+    m_rem = int((er != 0).sum())
+    return {
+        "wall_s": wall, "m_removed": m_rem, "rounds": int(summ[0]), "edge_rounds": int(summ[1]),
+        "core_vertices": int(summ[3]),
+        "build_ms": float(np.mean(tb.ms)), "peel_ms": float(np.mean(tp.ms)),
+        "peel_bytes": peel_bytes(n, r, e_host, deg0, vr, er),
+        "build_bytes": build_bytes(n, m, r), "edges_host": e_host,
+    }
+
+
+def bench_iblt(spec, reps):
+    keys_h = spec.keys(1)
+    dev = torch.device("cuda", 0)
+    keys = torch.from_numpy(keys_h.view(np.int64)).to(dev)
+    pinned = torch.from_numpy(keys_h.view(np.int64)).pin_memory()
+    d = pk.iblt_desc(spec.ncells, spec.r, spec.table_seed(1))
+    cells = pk.iblt_table(spec.ncells, dev)
+    lo = pk.ListOut(torch.empty(spec.ncells, dtype=torch.int64, device=dev),
+                    torch.empty(4096, dtype=torch.int64, device=dev),
+                    torch.empty(8, dtype=torch.int64, device=dev))
+    ws = pk.workspace(pk.iblt_list_workspace(d), dev)
+    ti, tl, th = Timer(), Timer(), Timer()
+    for i in range(reps + 2):
+        cells.zero_()
+        with th:
+            keys.copy_(pinned, non_blocking=True)
+            pk.iblt_insert(d, cells, keys)
+        th.collect()
+        cells.zero_()
+        with ti:
+            pk.iblt_insert(d, cells, keys)
+        ti.collect()
+        with tl:
+            pk.iblt_list(d, cells, max_rounds=4096, out=lo, ws=ws)
+        tl.collect()
+    s = lo.summary.cpu().numpy()
+    listed = int(s[0])
+    ins = float(np.median(ti.ms[2:]))
+    lst = float(np.median(tl.ms[2:]))
+    h2d = float(np.median(th.ms[2:]))
+    return {
+        "workload": spec.name, "cells": spec.ncells, "keys": spec.nkeys, "r": spec.r,
+        "listed": listed, "rounds": int(s[1]), "left": int(s[2]), "flags": int(s[3]),
+        "insert_ms": ins, "list_ms": lst, "insert_incl_h2d_ms": h2d,
+        "insert_keys_per_s": spec.nkeys / (ins * 1e-3),
+        "list_keys_per_s": listed / (lst * 1e-3),
+        "insert_gbs": iblt_insert_bytes(spec.nkeys, spec.r) / (ins * 1e-3) / 1e9,
+        "list_gbs": iblt_list_bytes(spec.ncells, spec.r, listed) / (lst * 1e-3) / 1e9,
+    }
+
+
+def cpu_baseline(spec, e_host):
+    """The oracle's round-synchronous peel on the same workload, single-threaded."""
+    from oracle import native  # CPU-baseline leg only
+    t0 = time.perf_counter()
+    o = native.peel_rounds(spec.n, e_host, spec.k)
+    dt = time.perf_counter() - t0
+    m_rem = int((o.edge_round != 0).sum())
+    return {"value": m_rem / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full run of oracle peel_rounds (its own CSR build included) on "
+                      f"{spec.name} ({spec.m} edges), {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-iblt", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="also time every c of the n=2^24 sweep")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the peel and the IBLT listing run on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    pk.lib()
+
+    spec = configs.kcore_sweep(0.70)
+    kc = bench_kcore(spec, args.steps, args.warmup)
+    ms_step = kc["wall_s"] / args.steps * 1e3
+    value = kc["m_removed"] / (kc["wall_s"] / args.steps)
+    # dominant kernel: the longer of the two calls
+    if kc["peel_ms"] >= kc["build_ms"]:
+        dom, dom_ms, dom_bytes = "k_peel_persistent", kc["peel_ms"], kc["peel_bytes"]
+    else:
+        dom, dom_ms, dom_bytes = "hg_build", kc["build_ms"], kc["build_bytes"]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    extra = {
+        "peel_ms": kc["peel_ms"], "build_ms": kc["build_ms"],
+        "peel_edges_per_s": kc["m_removed"] / (kc["peel_ms"] * 1e-3),
+        "peel_algorithmic_bytes": kc["peel_bytes"], "build_algorithmic_bytes": kc["build_bytes"],
+        "peel_gbs": kc["peel_bytes"] / (kc["peel_ms"] * 1e-3) / 1e9,
+        "build_gbs": kc["build_bytes"] / (kc["build_ms"] * 1e-3) / 1e9,
+        "rounds": kc["rounds"], "edge_rounds": kc["edge_rounds"],
+        "core_vertices": kc["core_vertices"],
+    }
+    if not args.no_iblt:
+        log("IBLT 2^24 cells")
+        extra["iblt"] = [bench_iblt(configs.iblt_main(), 5),
+                         bench_iblt(configs.iblt_paper(3, 0.75), 5)]
+    if args.sweep:
+        sw = []
+        for c in configs.SWEEP_C:
+            s2 = configs.kcore_sweep(c)
+            r2 = bench_kcore(s2, max(3, args.steps // 4), 1)
+            sw.append({"workload": s2.name, "m": s2.m, "rounds": r2["rounds"],
+                       "m_removed": r2["m_removed"], "peel_ms": r2["peel_ms"],
+                       "build_ms": r2["build_ms"],
+                       "peel_gbs": r2["peel_bytes"] / (r2["peel_ms"] * 1e-3) / 1e9})
+        extra["sweep"] = sw
+    line = {
+        "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": spec.name, "n": spec.n, "m": spec.m, "r": spec.r, "k": spec.k,
+                   "model": spec.model, "seed": 1, "step": "hg_build + peel_kcore"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "extra": extra,
+    }
+    if not args.no_cpu:
+        log("oracle CPU baseline")
+        line["cpu_baseline"] = cpu_baseline(spec, kc["edges_host"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

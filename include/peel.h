@@ -109,9 +109,10 @@ peel_status hg_build(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n,
  *   max_rounds       >= 1.  If round max_rounds+1 would still remove a vertex,
  *                    the run stops and sets PEEL_FLAG_EROUNDS; the outputs
  *                    then hold the state after max_rounds rounds.
- *   summary          (device, out) 4 uint32: [0] rounds (last round that
+ *   summary          (device, out) 8 uint32: [0] rounds (last round that
  *                    removed a vertex), [1] last round that removed an edge,
- *                    [2] status flags, [3] number of core vertices.
+ *                    [2] status flags, [3] number of core vertices, [4] the
+ *                    workgroups that ran the rounds (diagnostic), [5..7] 0.
  *   ws               (device) ws_bytes >= peel_kcore_workspace(n, m, r).
  */
 size_t peel_kcore_workspace(uint32_t n, uint64_t m, uint32_t r);
@@ -174,11 +175,12 @@ peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, const uint64_t 
  *                stops before that round and sets PEEL_FLAG_ENOSPC.
  *   round_stats  (device, out) max_rounds uint64: K_t per round.
  *   max_rounds   >= 1; PEEL_FLAG_EROUNDS as for peel_kcore.
- *   summary      (device, out) 4 uint64: [0] keys listed, [1] rounds, [2]
+ *   summary      (device, out) 8 uint64: [0] keys listed, [1] rounds, [2]
  *                keys still in the table (sum of counts / r minus [0]; 0 means
  *                the table was emptied), [3] status flags (PEEL_FLAG_ECORRUPT
  *                if a count-1 cell failed its checksum; such a cell is not
- *                pure).
+ *                pure), [4] the workgroups that ran the rounds (diagnostic),
+ *                [5..7] 0.
  *   ws           (device) ws_bytes >= iblt_list_workspace(desc).
  */
 size_t iblt_list_workspace(const iblt_desc *desc);

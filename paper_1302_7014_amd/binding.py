@@ -131,7 +131,7 @@ class PeelOut:
     vertex_round: torch.Tensor  # int32[n]
     edge_round: torch.Tensor    # int32[m]
     round_stats: torch.Tensor   # int64[2*max_rounds]
-    summary: torch.Tensor       # int32[4]: rounds, edge rounds, flags, core vertices
+    summary: torch.Tensor       # int32[8]: rounds, edge rounds, flags, core vertices, team
 
 
 def peel_kcore_workspace(n: int, m: int, r: int) -> int:
@@ -149,7 +149,7 @@ def peel_kcore(edges: torch.Tensor, n: int, k: int, csr: Csr, max_rounds: int = 
     dev = edges.device
     if out is None:
         out = PeelOut(csr.deg, _empty(n, torch.int32, dev), _empty(m, torch.int32, dev),
-                      _empty(2 * max_rounds, torch.int64, dev), _empty(4, torch.int32, dev))
+                      _empty(2 * max_rounds, torch.int64, dev), _empty(8, torch.int32, dev))
     if ws is None:
         ws = workspace(peel_kcore_workspace(n, m, r), dev)
     _check(lib().peel_kcore(_ptr(edges), m, r, n, k, _ptr(csr.offsets), _ptr(csr.inc),
@@ -178,7 +178,7 @@ def iblt_insert(desc: IbltDesc, cells: torch.Tensor, keys: torch.Tensor, stream=
 class ListOut:
     keys: torch.Tensor         # int64[out_cap]
     round_stats: torch.Tensor  # int64[max_rounds]: keys listed per round
-    summary: torch.Tensor      # int64[4]: listed, rounds, keys left, flags
+    summary: torch.Tensor      # int64[8]: listed, rounds, keys left, flags, team
 
 
 def iblt_list_workspace(desc: IbltDesc) -> int:
@@ -193,7 +193,7 @@ def iblt_list(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = None,
     if out is None:
         cap = desc.ncells if out_cap is None else out_cap
         out = ListOut(_empty(cap, torch.int64, dev), _empty(max_rounds, torch.int64, dev),
-                      _empty(4, torch.int64, dev))
+                      _empty(8, torch.int64, dev))
     cap = out.keys.numel() if out_cap is None else out_cap
     if ws is None:
         ws = workspace(iblt_list_workspace(desc), dev)

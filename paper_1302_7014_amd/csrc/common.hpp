@@ -78,12 +78,31 @@ __device__ inline uint32_t block_sum(uint32_t v, uint32_t *lds) {
   return total;
 }
 
+// Maximum of one value per thread across the workgroup (every thread calls it).
+__device__ inline uint32_t block_max(uint32_t v, uint32_t *lds) {
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const uint32_t o = __shfl_xor(v, d, kWave);
+    v = o > v ? o : v;
+  }
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = v;
+  __syncthreads();
+  uint32_t m = 0;
+  for (int w = 0; w < kBlock / kWave; ++w) m = lds[w] > m ? lds[w] : m;
+  __syncthreads();
+  return m;
+}
+
 // ---------------------------------------------------------------------------
-// Device-wide barrier for persistent kernels launched cooperatively (every
-// workgroup resident).  Workgroups arrive on `count`; the last one resets it
-// and advances `gen`; the others wait for `gen` to move.  A wait that passes
-// `limit` wall-clock ticks, or that sees `abort` set, sets `abort` and
-// returns false: the caller then leaves the kernel, so every wave ends.
+// Device-wide barrier among the `nblocks` members of a team (every member is
+// resident).  One thread per workgroup takes part: it makes the workgroup's
+// writes visible device-wide (one release fence, which writes back the XCD's
+// L2), arrives on `count`, and polls `gen` with relaxed loads (a poll with
+// acquire semantics would invalidate the L2 on every iteration and starve the
+// workgroups still working), then takes one acquire fence.  The last arriver
+// acquires everyone's writes, resets `count` and releases the new `gen`.  A
+// wait longer than `limit` wall-clock ticks, or one that sees `abort`, sets
+// `abort` and returns false; the caller then leaves the kernel, so every wave
+// ends.  `stamp`, when not null, receives the wall clock of each generation.
 struct GridSync {
   uint32_t count;
   uint32_t gen;
@@ -91,24 +110,27 @@ struct GridSync {
   uint32_t pad;
 };
 
-__device__ inline bool grid_barrier(GridSync *gs, uint32_t nblocks, uint64_t limit) {
+__device__ inline bool grid_barrier(GridSync *gs, uint32_t nblocks, uint64_t limit,
+                                    uint64_t *stamp = nullptr) {
   __shared__ uint32_t s_ok;
-  __threadfence();  // publish this thread's writes device-wide
-  __syncthreads();
+  __syncthreads();  // every wave's stores of this workgroup have completed
   if (threadIdx.x == 0) {
     uint32_t ok = 1;
     if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       ok = 0;
     } else {
-      const uint32_t g = __hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t g = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const uint32_t arrived =
-          __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (arrived == nblocks - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (stamp) stamp[g & 255] = wall_clock64();
         __hip_atomic_store(&gs->gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         const uint64_t t0 = wall_clock64();
-        while (__hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        while (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
           if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             ok = 0;
             break;
@@ -118,15 +140,84 @@ __device__ inline bool grid_barrier(GridSync *gs, uint32_t nblocks, uint64_t lim
             ok = 0;
             break;
           }
-          __builtin_amdgcn_s_sleep(1);
+          __builtin_amdgcn_s_sleep(2);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
     }
     s_ok = ok;
   }
   __syncthreads();
-  __threadfence();  // see every other workgroup's writes from before the barrier
   return s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Team of resident workgroups for a persistent kernel.  A device-wide barrier
+// is only safe among workgroups that are running at the same time, and the
+// number the hardware keeps resident is not reliably the occupancy estimate.
+// So the team is formed at run time: every workgroup adds one to `join`; the
+// first (slot 0) waits until all gridDim.x workgroups have joined, or until no
+// new one has joined for `quiet` ticks, then sets the CLOSED bit and publishes
+// the count as `size`.  Workgroups that joined before the close are members
+// (they are running, hence resident); later ones see CLOSED and leave at once.
+// Members use their slot and the team size in place of blockIdx.x/gridDim.x.
+struct Team {
+  uint32_t join;
+  uint32_t size;
+};
+
+constexpr uint32_t kTeamClosed = 0x80000000u;
+
+// True for a member; `slot` and `size` then hold its index and the team size.
+__device__ inline bool team_join(Team *tm, uint64_t quiet, uint64_t limit, uint32_t *slot,
+                                 uint32_t *size) {
+  __shared__ uint32_t s_slot, s_size;
+  if (threadIdx.x == 0) {
+    uint32_t sl = 0xffffffffu, sz = 0;
+    const uint32_t old =
+        __hip_atomic_fetch_add(&tm->join, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!(old & kTeamClosed)) {
+      sl = old;
+      if (old == 0) {
+        const uint64_t t0 = wall_clock64();
+        uint64_t last = t0;
+        uint32_t seen = 1;
+        for (;;) {
+          const uint32_t c =
+              __hip_atomic_load(&tm->join, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+              ~kTeamClosed;
+          if (c >= gridDim.x) break;
+          const uint64_t now = wall_clock64();
+          if (c != seen) {
+            seen = c;
+            last = now;
+          } else if (now - last > quiet) {
+            break;
+          }
+          if (now - t0 > limit) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        sz = __hip_atomic_fetch_or(&tm->join, kTeamClosed, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) &
+             ~kTeamClosed;
+        __hip_atomic_store(&tm->size, sz, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        const uint64_t t0 = wall_clock64();
+        while ((sz = __hip_atomic_load(&tm->size, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ==
+               0) {
+          if (wall_clock64() - t0 > limit) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+    }
+    s_slot = sl;
+    s_size = sz;
+  }
+  __syncthreads();
+  *slot = s_slot;
+  *size = s_size;
+  return s_size != 0 && s_slot < s_size;
 }
 
 // ---------------------------------------------------------------------------

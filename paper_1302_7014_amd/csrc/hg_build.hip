@@ -15,7 +15,8 @@ constexpr int kScanTile = kBlock * kScanItems;     // 2048 degrees per workgroup
 
 struct BuildWs {
   uint32_t *cursor;  // n
-  uint32_t *part;    // tiles
+  uint32_t *part;    // tiles: degree sum per tile, then its exclusive prefix
+  uint32_t *pmax;    // tiles: maximum degree per tile
 };
 
 inline size_t scan_tiles(uint32_t n) { return (n + kScanTile - 1) / kScanTile; }
@@ -39,9 +40,9 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// part[b] = sum of deg over tile b; info[1] = max degree.
+// part[b] = sum of deg over tile b; pmax[b] = its maximum.
 __global__ void __launch_bounds__(kBlock)
-    k_tile_sums(const uint32_t *__restrict__ deg, uint32_t n, uint32_t *part, uint32_t *info) {
+    k_tile_sums(const uint32_t *__restrict__ deg, uint32_t n, uint32_t *part, uint32_t *pmax) {
   __shared__ uint32_t lds[kBlock / kWave + 1];
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
   uint32_t s = 0, mx = 0;
@@ -56,19 +57,20 @@ __global__ void __launch_bounds__(kBlock)
   }
   const uint32_t tot = block_sum(s, lds);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
-  // wave max, then one atomic per wave
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    const uint32_t o = __shfl_xor(mx, d, kWave);
-    mx = o > mx ? o : mx;
-  }
-  if (lane_id() == 0 && mx) atomicMax(&info[1], mx);
+  const uint32_t bmax = block_max(mx, lds);
+  if (threadIdx.x == 0) pmax[blockIdx.x] = bmax;
 }
 
-// Exclusive scan of part[0..tiles) in place by one workgroup; offsets[n] = total.
+// Exclusive scan of part[0..tiles) in place by one workgroup; offsets[n] =
+// total; info[1] = maximum of pmax.
 __global__ void __launch_bounds__(kBlock)
-    k_scan_parts(uint32_t *part, uint64_t tiles, uint32_t *offsets, uint32_t n) {
+    k_scan_parts(uint32_t *part, const uint32_t *pmax, uint64_t tiles, uint32_t *offsets,
+                 uint32_t n, uint32_t *info) {
   __shared__ uint32_t lds[kBlock / kWave + 1];
-  uint32_t carry = 0;
+  uint32_t carry = 0, mx = 0;
+  for (uint64_t b = threadIdx.x; b < tiles; b += kBlock) mx = pmax[b] > mx ? pmax[b] : mx;
+  mx = block_max(mx, lds);
+  if (threadIdx.x == 0) info[1] = mx;
   for (uint64_t b0 = 0; b0 < tiles; b0 += (uint64_t)kBlock * kScanItems) {
     const uint64_t base = b0 + (uint64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
@@ -162,7 +164,7 @@ peel_status dispatch_edges(uint32_t r, bool scatter, const uint32_t *edges, uint
 }
 
 size_t build_ws_bytes(uint32_t n) {
-  return align_up((size_t)n * 4) + align_up(scan_tiles(n) * 4) + 256;
+  return align_up((size_t)n * 4) + 2 * align_up(scan_tiles(n) * 4) + 256;
 }
 
 }  // namespace
@@ -185,7 +187,7 @@ extern "C" peel_status hg_build(const uint32_t *edges, uint64_t m, uint32_t r, u
   if (ws_bytes < build_ws_bytes(n)) return PEEL_ENOSPC;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Carver c(ws);
-  BuildWs w{c.take<uint32_t>(n), c.take<uint32_t>(scan_tiles(n))};
+  BuildWs w{c.take<uint32_t>(n), c.take<uint32_t>(scan_tiles(n)), c.take<uint32_t>(scan_tiles(n))};
   const uint64_t tiles = scan_tiles(n);
 
   hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s,
@@ -194,8 +196,9 @@ extern "C" peel_status hg_build(const uint32_t *edges, uint64_t m, uint32_t r, u
   PEEL_HIP_TRY(hipGetLastError());
   peel_status st = dispatch_edges(r, false, edges, m, n, deg, info, s);
   if (st) return st;
-  hipLaunchKernelGGL(k_tile_sums, dim3(tiles), dim3(kBlock), 0, s, deg, n, w.part, info);
-  hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, s, w.part, tiles, offsets, n);
+  hipLaunchKernelGGL(k_tile_sums, dim3(tiles), dim3(kBlock), 0, s, deg, n, w.part, w.pmax);
+  hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, s, w.part, w.pmax, tiles, offsets,
+                     n, info);
   hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, deg, n, w.part, offsets,
                      w.cursor);
   PEEL_HIP_TRY(hipGetLastError());

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
 
 #include "peel.h"
@@ -35,8 +37,19 @@ struct Carver {
 struct DeviceInfo {
   int id = -1;
   int cus = 0;
-  uint64_t barrier_limit_ticks = 0;  // ~10 s of the device wall clock
+  int blocks_per_cu_cap = 0;         // PEEL_BLOCKS_PER_CU, 0 = occupancy only
+  uint64_t barrier_limit_ticks = 0;  // PEEL_BARRIER_TIMEOUT_MS of device wall clock (10 s)
+  uint64_t team_quiet_ticks = 0;     // PEEL_TEAM_QUIET_US of device wall clock (5 us)
+  bool debug = false;                // PEEL_DEBUG: launch shapes on stderr
 };
+
+inline long env_long(const char *name, long dflt) {
+  const char *v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  char *end = nullptr;
+  long x = std::strtol(v, &end, 10);
+  return (end && *end == 0) ? x : dflt;
+}
 
 // Properties of the current device (cached per device id).
 inline const DeviceInfo &device_info() {
@@ -52,7 +65,15 @@ inline const DeviceInfo &device_info() {
     (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
     if (khz <= 0) khz = 100000;  // 100 MHz
     d.cus = cus > 0 ? cus : 1;
-    d.barrier_limit_ticks = (uint64_t)khz * 1000ull * 10ull;
+    long ms = env_long("PEEL_BARRIER_TIMEOUT_MS", 10000);
+    if (ms < 1) ms = 1;
+    d.barrier_limit_ticks = (uint64_t)khz * (uint64_t)ms;
+    long us = env_long("PEEL_TEAM_QUIET_US", 5);
+    if (us < 1) us = 1;
+    d.team_quiet_ticks = (uint64_t)khz * (uint64_t)us / 1000ull + 1;
+    long cap = env_long("PEEL_BLOCKS_PER_CU", 0);
+    d.blocks_per_cu_cap = cap > 0 ? (int)cap : 0;
+    d.debug = env_long("PEEL_DEBUG", 0) != 0;
     d.id = dev;
   }
   return d;
@@ -60,11 +81,16 @@ inline const DeviceInfo &device_info() {
 
 // Workgroups of `kernel` (kBlock threads) that fit on the device at once.
 inline int coresident_blocks(const void *kernel, int block, size_t lds_bytes) {
+  const DeviceInfo &d = device_info();
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds_bytes) != hipSuccess ||
       per_cu <= 0)
     per_cu = 1;
-  return per_cu * device_info().cus;
+  const int occ = per_cu;
+  if (d.blocks_per_cu_cap > 0 && per_cu > d.blocks_per_cu_cap) per_cu = d.blocks_per_cu_cap;
+  if (d.debug)
+    std::fprintf(stderr, "[peel] occupancy %d blocks/CU, using %d x %d CUs\n", occ, per_cu, d.cus);
+  return per_cu * d.cus;
 }
 
 inline unsigned grid_for(uint64_t items, int per_block, unsigned cap = 1u << 20) {

@@ -28,7 +28,10 @@
 namespace peel {
 namespace {
 
-constexpr int kQueue = 4096;
+#ifndef PEEL_LDS_QUEUE
+#define PEEL_LDS_QUEUE 4096
+#endif
+constexpr int kQueue = PEEL_LDS_QUEUE;
 constexpr int kDenseItems = 4;  // cells per thread in the dense pass
 constexpr int kDenseTile = kBlock * kDenseItems;
 
@@ -89,12 +92,14 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 struct ListCtrl {
   GridSync sync;
+  Team team;
   uint32_t own[3];   // keys owned in the detect phase feeding round t: own[t % 3]
   uint32_t cand[2];  // candidates pushed in round t: cand[t % 2]
   uint32_t flags;
   uint32_t rounds;
   uint64_t listed;
   unsigned long long count_sum;  // sum of all counts at the start (two's complement)
+  uint64_t stamp[256];           // wall clock at each barrier generation (diagnostic)
 };
 
 struct ListArgs {
@@ -107,6 +112,7 @@ struct ListArgs {
   uint32_t *cb;
   ListCtrl *ctrl;
   uint64_t limit;
+  uint64_t quiet;
   uint32_t ncells;
   uint32_t max_rounds;
 };
@@ -114,6 +120,7 @@ struct ListArgs {
 __global__ void k_list_init(ListCtrl *ctrl) {
   if (threadIdx.x == 0) {
     ctrl->sync.count = ctrl->sync.gen = ctrl->sync.abort = ctrl->sync.pad = 0;
+    ctrl->team.join = ctrl->team.size = 0;
     ctrl->own[0] = ctrl->own[1] = ctrl->own[2] = 0;
     ctrl->cand[0] = ctrl->cand[1] = 0;
     ctrl->flags = 0;
@@ -169,10 +176,11 @@ __global__ void __launch_bounds__(kBlock) k_list_persistent(ListArgs a) {
   __shared__ uint32_t lds[kBlock / kWave + 1];
   __shared__ unsigned long long s_sum;
 
-  const uint32_t nblocks = gridDim.x;
-  const uint64_t gtid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint64_t gsize = (uint64_t)nblocks * kBlock;
   ListCtrl *ctrl = a.ctrl;
+  uint32_t slot, nblocks;
+  if (!team_join(&ctrl->team, a.quiet, a.limit, &slot, &nblocks)) return;
+  const uint64_t gtid = (uint64_t)slot * kBlock + threadIdx.x;
+  const uint64_t gsize = (uint64_t)nblocks * kBlock;
   uint32_t bad = 0;
 
   // ---- round-1 detect over every cell -------------------------------------
@@ -180,7 +188,7 @@ __global__ void __launch_bounds__(kBlock) k_list_persistent(ListArgs a) {
   if (threadIdx.x == 0) s_sum = 0;
   __syncthreads();
   long long local_sum = 0;
-  for (uint64_t t0 = (uint64_t)blockIdx.x * kDenseTile; t0 < a.ncells;
+  for (uint64_t t0 = (uint64_t)slot * kDenseTile; t0 < a.ncells;
        t0 += (uint64_t)nblocks * kDenseTile) {
 #pragma unroll
     for (int it = 0; it < kDenseItems; ++it) {
@@ -201,7 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_list_persistent(ListArgs a) {
   if (threadIdx.x == 0 && s_sum) atomicAdd(&ctrl->count_sum, s_sum);
   if (bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
   bad = 0;
-  if (!grid_barrier(&ctrl->sync, nblocks, a.limit)) return;
+  if (!grid_barrier(&ctrl->sync, nblocks, a.limit, ctrl->stamp)) return;
 
   // ---- rounds ---------------------------------------------------------------
   uint64_t listed = 0;
@@ -250,7 +258,7 @@ __global__ void __launch_bounds__(kBlock) k_list_persistent(ListArgs a) {
     if (threadIdx.x == 0) s_base = nq ? atomicAdd(cctr, nq) : 0u;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nq; i += kBlock) cand[s_base + i] = q[i];
-    if (!grid_barrier(&ctrl->sync, nblocks, a.limit)) return;
+    if (!grid_barrier(&ctrl->sync, nblocks, a.limit, ctrl->stamp)) return;
 
     // detect for round t+1 over this round's candidates
     listed += K;
@@ -269,7 +277,7 @@ __global__ void __launch_bounds__(kBlock) k_list_persistent(ListArgs a) {
     }
     if (bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
     bad = 0;
-    if (!grid_barrier(&ctrl->sync, nblocks, a.limit)) return;
+    if (!grid_barrier(&ctrl->sync, nblocks, a.limit, ctrl->stamp)) return;
   }
   if (gtid == 0) {
     ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
@@ -277,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_list_persistent(ListArgs a) {
   }
 }
 
-// summary = [listed, rounds, keys left, flags].
+// summary = [listed, rounds, keys left, flags, workgroups in the persistent team, 0, 0, 0].
 __global__ void k_list_finish(const ListCtrl *ctrl, uint32_t r, uint64_t *summary) {
   if (threadIdx.x != 0) return;
   const long long total = (long long)ctrl->count_sum;
@@ -288,6 +296,8 @@ __global__ void k_list_finish(const ListCtrl *ctrl, uint32_t r, uint64_t *summar
   summary[1] = ctrl->rounds;
   summary[2] = (uint64_t)(keys - (long long)ctrl->listed);
   summary[3] = flags;
+  summary[4] = ctrl->team.size;
+  summary[5] = summary[6] = summary[7] = 0;
 }
 
 size_t list_ws_bytes(uint64_t ncells) {
@@ -314,8 +324,10 @@ peel_status launch_list(ListArgs &a, hipStream_t s) {
   uint64_t want = ((uint64_t)a.ncells + kDenseTile - 1) / kDenseTile;
   if (want < 1) want = 1;
   const unsigned grid = static_cast<unsigned>(want < (uint64_t)cap ? want : (uint64_t)cap);
-  void *args[] = {&a};
-  PEEL_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, s));
+  if (device_info().debug) std::fprintf(stderr, "[peel] persistent grid %u (cap %d)\n", grid, cap);
+  // A plain launch: the kernel forms its team of resident workgroups itself.
+  hipLaunchKernelGGL(k_list_persistent<R>, dim3(grid), dim3(kBlock), 0, s, a);
+  PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }
 
@@ -364,6 +376,7 @@ extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64
   a.out_cap = out_cap;
   a.stats = round_stats;
   a.limit = device_info().barrier_limit_ticks;
+  a.quiet = device_info().team_quiet_ticks;
   a.ncells = static_cast<uint32_t>(desc->ncells);
   a.max_rounds = max_rounds;
   hipLaunchKernelGGL(k_list_init, dim3(1), dim3(64), 0, s, a.ctrl);

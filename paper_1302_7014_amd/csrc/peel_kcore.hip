@@ -8,7 +8,7 @@
 // compare-and-swap (0 -> t), so exactly one of the peeled vertices that share
 // an edge removes it.
 //
-// One persistent, cooperatively launched kernel runs every round, with a
+// One persistent kernel (a run-time team of resident workgroups) runs every round, with a
 // device-wide barrier between rounds and no host round trip:
 //   phase 0   dense pass: zero edge rounds and stats, mark vertex_round = 1 and
 //             compact F_1 = {v : deg(v) < k} (block prefix sum, one atomic per
@@ -31,17 +31,22 @@
 namespace peel {
 namespace {
 
-constexpr int kQueue = 4096;          // LDS push-queue entries per workgroup
+#ifndef PEEL_LDS_QUEUE
+#define PEEL_LDS_QUEUE 4096
+#endif
+constexpr int kQueue = PEEL_LDS_QUEUE;          // LDS push-queue entries per workgroup
 constexpr int kDenseItems = 8;        // vertices per thread in the dense pass
 constexpr int kDenseTile = kBlock * kDenseItems;
 
 struct PeelCtrl {
   GridSync sync;
+  Team team;
   uint32_t fcount[3];  // |F_t| lives in fcount[t % 3]
   uint32_t flags;
   uint32_t rounds;
   uint32_t pad;
   uint64_t removed;
+  uint64_t stamp[256];  // wall clock at each barrier generation (diagnostic)
 };
 
 struct PeelArgs {
@@ -57,6 +62,7 @@ struct PeelArgs {
   PeelCtrl *ctrl;
   uint64_t m;
   uint64_t limit;
+  uint64_t quiet;
   uint32_t n;
   uint32_t k;
   uint32_t max_rounds;
@@ -68,6 +74,8 @@ __global__ void k_peel_init(PeelCtrl *ctrl) {
     ctrl->sync.gen = 0;
     ctrl->sync.abort = 0;
     ctrl->sync.pad = 0;
+    ctrl->team.join = 0;
+    ctrl->team.size = 0;
     ctrl->fcount[0] = ctrl->fcount[1] = ctrl->fcount[2] = 0;
     ctrl->flags = 0;
     ctrl->rounds = 0;
@@ -83,15 +91,16 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
   __shared__ uint32_t s_base;
   __shared__ uint32_t lds[kBlock / kWave + 1];
 
-  const uint32_t nblocks = gridDim.x;
-  const uint64_t gtid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint64_t gsize = (uint64_t)nblocks * kBlock;
   PeelCtrl *ctrl = a.ctrl;
+  uint32_t slot, nblocks;
+  if (!team_join(&ctrl->team, a.quiet, a.limit, &slot, &nblocks)) return;
+  const uint64_t gtid = (uint64_t)slot * kBlock + threadIdx.x;
+  const uint64_t gsize = (uint64_t)nblocks * kBlock;
 
   // ---- phase 0 ------------------------------------------------------------
   for (uint64_t e = gtid; e < a.m; e += gsize) a.er[e] = 0;
   for (uint64_t i = gtid; i < 2ull * a.max_rounds; i += gsize) a.stats[i] = 0;
-  for (uint64_t t0 = (uint64_t)blockIdx.x * kDenseTile; t0 < a.n;
+  for (uint64_t t0 = (uint64_t)slot * kDenseTile; t0 < a.n;
        t0 += (uint64_t)nblocks * kDenseTile) {
     const uint64_t base = t0 + (uint64_t)threadIdx.x * kDenseItems;
     uint32_t low = 0, cnt = 0;
@@ -115,7 +124,7 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
       if (low >> i & 1u) a.fa[pos++] = static_cast<uint32_t>(base + i);
     __syncthreads();
   }
-  if (!grid_barrier(&ctrl->sync, nblocks, a.limit)) return;
+  if (!grid_barrier(&ctrl->sync, nblocks, a.limit, ctrl->stamp)) return;
 
   // ---- rounds -------------------------------------------------------------
   uint32_t t = 1;
@@ -147,7 +156,9 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
       const uint32_t end = a.offsets[v + 1];
       for (uint32_t p = beg; p < end; ++p) {
         const uint32_t e = a.inc[p];
-        if (e >= a.m || atomic_load_u32(&a.er[e]) != 0u) continue;
+        // A plain read may be stale only towards 0 (a claim it has not seen yet);
+        // the compare-and-swap below settles those.
+        if (e >= a.m || a.er[e] != 0u) continue;
         if (atomicCAS(&a.er[e], 0u, t) != 0u) continue;
         ++wins;
         const uint32_t *row = a.edges + (uint64_t)e * R;
@@ -178,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
     for (uint32_t i = threadIdx.x; i < nq; i += kBlock) nxt[s_base + i] = q[i];
     const uint32_t bw = block_sum(wins, lds);
     if (threadIdx.x == 0 && bw) atomicAdd(&a.stats[2ull * (t - 1) + 1], (uint64_t)bw);
-    if (!grid_barrier(&ctrl->sync, nblocks, a.limit)) return;
+    if (!grid_barrier(&ctrl->sync, nblocks, a.limit, ctrl->stamp)) return;
   }
   if (gtid == 0) {
     ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
@@ -186,7 +197,8 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
   }
 }
 
-// summary = [rounds, last round that removed an edge, flags, core vertices].
+// summary = [rounds, last round that removed an edge, flags, core vertices,
+//            workgroups in the persistent team, 0, 0, 0].
 __global__ void k_peel_finish(const PeelCtrl *ctrl, const uint64_t *stats, uint32_t n,
                               uint32_t *summary) {
   if (threadIdx.x != 0) return;
@@ -203,6 +215,8 @@ __global__ void k_peel_finish(const PeelCtrl *ctrl, const uint64_t *stats, uint3
   summary[1] = last_e;
   summary[2] = flags;
   summary[3] = static_cast<uint32_t>(n - ctrl->removed);
+  summary[4] = ctrl->team.size;
+  summary[5] = summary[6] = summary[7] = 0;
 }
 
 size_t peel_ws_bytes(uint32_t n) { return align_up(sizeof(PeelCtrl)) + 2 * align_up((size_t)n * 4); }
@@ -216,8 +230,10 @@ peel_status launch(PeelArgs &a, hipStream_t s) {
   if (want_m > want) want = want_m;
   if (want < 1) want = 1;
   const unsigned grid = static_cast<unsigned>(want < (uint64_t)cap ? want : (uint64_t)cap);
-  void *args[] = {&a};
-  PEEL_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, s));
+  if (device_info().debug) std::fprintf(stderr, "[peel] persistent grid %u (cap %d)\n", grid, cap);
+  // A plain launch: the kernel forms its team of resident workgroups itself.
+  hipLaunchKernelGGL(k_peel_persistent<R>, dim3(grid), dim3(kBlock), 0, s, a);
+  PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }
 
@@ -261,6 +277,7 @@ extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r,
   a.k = k;
   a.max_rounds = max_rounds;
   a.limit = device_info().barrier_limit_ticks;
+  a.quiet = device_info().team_quiet_ticks;
 
   hipLaunchKernelGGL(k_peel_init, dim3(1), dim3(64), 0, s, a.ctrl);
   PEEL_HIP_TRY(hipGetLastError());
