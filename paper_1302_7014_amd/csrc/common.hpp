@@ -48,8 +48,9 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
   return v;
 }
 
-// Exclusive scan of one value per thread across a kBlock-thread workgroup.
-// `lds` holds kBlock/kWave + 1 words.  Every thread must call it.
+// Exclusive scan of one value per thread across an NT-thread workgroup.
+// `lds` holds NT/kWave + 1 words.  Every thread must call it.
+template <int NT = kBlock>
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total, uint32_t *lds) {
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
@@ -58,27 +59,29 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total, uin
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
-    for (int w = 0; w < kBlock / kWave; ++w) {
+    for (int w = 0; w < NT / kWave; ++w) {
       uint32_t t = lds[w];
       lds[w] = acc;
       acc += t;
     }
-    lds[kBlock / kWave] = acc;
+    lds[NT / kWave] = acc;
   }
   __syncthreads();
   uint32_t out = lds[wave] + inc - v;
-  *total = lds[kBlock / kWave];
+  *total = lds[NT / kWave];
   __syncthreads();
   return out;
 }
 
+template <int NT = kBlock>
 __device__ inline uint32_t block_sum(uint32_t v, uint32_t *lds) {
   uint32_t total;
-  (void)block_exclusive_scan(v, &total, lds);
+  (void)block_exclusive_scan<NT>(v, &total, lds);
   return total;
 }
 
 // Maximum of one value per thread across the workgroup (every thread calls it).
+template <int NT = kBlock>
 __device__ inline uint32_t block_max(uint32_t v, uint32_t *lds) {
   for (int d = kWave / 2; d > 0; d >>= 1) {
     const uint32_t o = __shfl_xor(v, d, kWave);
@@ -87,7 +90,7 @@ __device__ inline uint32_t block_max(uint32_t v, uint32_t *lds) {
   if (lane_id() == 0) lds[threadIdx.x / kWave] = v;
   __syncthreads();
   uint32_t m = 0;
-  for (int w = 0; w < kBlock / kWave; ++w) m = lds[w] > m ? lds[w] : m;
+  for (int w = 0; w < NT / kWave; ++w) m = lds[w] > m ? lds[w] : m;
   __syncthreads();
   return m;
 }
@@ -148,6 +151,109 @@ __device__ inline bool grid_barrier(GridSync *gs, uint32_t nblocks, uint64_t lim
     s_ok = ok;
   }
   __syncthreads();
+  return s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Hierarchical device-wide barrier that also sums one 48-bit value per
+// workgroup.  Members are split into up to kBarGroups groups (slot % groups);
+// each arrives on its group word (low 16 bits count arrivals, the rest sums the
+// values), the last of a group forwards the group's sum to the top word, and
+// the last group publishes the total and a new top generation.  Group leaders
+// pass the release down to their group.  Every poll is a relaxed load with a
+// short sleep; one thread per workgroup fences (release before arriving,
+// acquire after the wait).  Timeouts and `abort` behave as in grid_barrier.
+constexpr int kBarGroups = 16;
+
+struct alignas(128) BarGroup {
+  uint64_t word;
+  uint64_t base;  // sum of the values of the groups that reached the top before this one
+  uint32_t gen;
+  uint32_t pad[27];
+};
+
+struct alignas(128) SumBar {
+  uint64_t top;
+  uint32_t top_gen;
+  uint32_t abort;
+  uint64_t total[2];
+  uint64_t pad[12];
+  BarGroup grp[kBarGroups];
+};
+
+__device__ inline bool bar_wait(const uint32_t *gen, uint32_t e, uint32_t *abort, uint64_t limit) {
+  const uint64_t t0 = wall_clock64();
+  while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
+    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (wall_clock64() - t0 > limit) {
+      __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+// Returns false on timeout/abort (the caller leaves the kernel).  `epoch` is the
+// workgroup's count of barriers passed (thread 0's copy is the one used).
+// `*total` receives the sum of all values; `*prefix` (if given) the sum of the
+// values of the workgroups ordered before this one in this barrier (an
+// exclusive prefix in arrival order).
+__device__ inline bool sum_barrier(SumBar *sb, uint32_t nblocks, uint32_t slot, uint64_t value,
+                                   uint32_t *epoch, uint64_t limit, uint64_t *total,
+                                   uint64_t *stamp = nullptr, uint64_t *prefix = nullptr) {
+  __shared__ uint32_t s_ok;
+  __shared__ uint64_t s_total;
+  __shared__ uint64_t s_prefix;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ok = 1;
+    uint64_t tot = 0, pre = 0;
+    const uint32_t e = ++*epoch;
+    const uint32_t groups = nblocks < (uint32_t)kBarGroups ? nblocks : (uint32_t)kBarGroups;
+    const uint32_t g = slot % groups;
+    const uint32_t gsize = nblocks / groups + (g < nblocks % groups ? 1u : 0u);
+    BarGroup *gp = &sb->grp[g];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint64_t old = __hip_atomic_fetch_add(&gp->word, 1ull | (value << 16), __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if ((old & 0xffffull) + 1 == gsize) {
+      const uint64_t gsum = (old >> 16) + value;
+      __hip_atomic_store(&gp->word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      const uint64_t old2 = __hip_atomic_fetch_add(&sb->top, 1ull | (gsum << 16), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+      pre = (old2 >> 16) + (old >> 16);
+      __hip_atomic_store(&gp->base, old2 >> 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((old2 & 0xffffull) + 1 == groups) {
+        tot = (old2 >> 16) + gsum;
+        __hip_atomic_store(&sb->top, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sb->total[e & 1], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (stamp) stamp[e & 255] = wall_clock64();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_store(&sb->top_gen, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        ok = bar_wait(&sb->top_gen, e, &sb->abort, limit);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        tot = __hip_atomic_load(&sb->total[e & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (ok) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&gp->gen, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else {
+      ok = bar_wait(&gp->gen, e, &sb->abort, limit);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      tot = __hip_atomic_load(&sb->total[e & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      pre = __hip_atomic_load(&gp->base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + (old >> 16);
+    }
+    s_ok = ok;
+    s_total = tot;
+    s_prefix = pre;
+  }
+  __syncthreads();
+  *total = s_total;
+  if (prefix) *prefix = s_prefix;
   return s_ok != 0;
 }
 

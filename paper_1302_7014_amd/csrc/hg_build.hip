@@ -1,76 +1,76 @@
 // hg_build: vertex -> incident-edge lists (CSR) by counting sort.
 //
 // The peeling process removes each peeled vertex "together with its incident
-// edges" (paper, Section 1), so the peel needs each vertex's edge list.  Three
-// passes: degree histogram (one atomic per incidence), exclusive scan of the
-// degrees into offsets, and scatter of edge ids through per-vertex cursors.
+// edges" (paper, Section 1), so the peel needs each vertex's edge list.
+//
+// Device-scope atomics run at a fixed rate far below HBM bandwidth on this
+// GPU, so the build keeps them out of the per-incidence work.  It is a
+// two-level counting sort:
+//   1. bin count    each workgroup takes a tile of edges and counts, in LDS,
+//                   its incidences per bucket of 16384 consecutive vertices;
+//   2. scan         exclusive scan of the bucket-major (bucket, tile) counts;
+//   3. bin scatter  each tile writes its (vertex, edge) pairs into its slice of
+//                   every bucket (LDS cursors, coalesced runs);
+//   4. bucket build one workgroup per bucket counts degrees in LDS, scans them
+//                   into offsets and places the edge ids with LDS cursors.
+// Above 4096 buckets (n > 2^26) the LDS histograms do not fit and the build
+// falls back to one device atomic per incidence for the degrees and another
+// for the cursors.
 #include "common.hpp"
 #include "host.hpp"
 
 namespace peel {
 namespace {
 
-constexpr int kScanItems = 8;                      // degrees per thread in the scan
-constexpr int kScanTile = kBlock * kScanItems;     // 2048 degrees per workgroup
+constexpr int kScanItems = 8;                   // values per thread in the scans
+constexpr int kScanTile = kBlock * kScanItems;  // 2048 values per workgroup
+constexpr int kBinShift = 14;                   // 16384 vertices per bucket
+constexpr int kBinV = 1 << kBinShift;
+constexpr int kMaxBuckets = 4096;
+constexpr uint64_t kTileEdges = 16384;          // edges per bin tile
 
-struct BuildWs {
-  uint32_t *cursor;  // n
-  uint32_t *part;    // tiles: degree sum per tile, then its exclusive prefix
-  uint32_t *pmax;    // tiles: maximum degree per tile
-};
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline uint64_t scan_tiles(uint64_t count) { return ceil_div(count, kScanTile); }
+inline bool binned(uint32_t n) { return ceil_div(n, kBinV) <= kMaxBuckets; }
 
-inline size_t scan_tiles(uint32_t n) { return (n + kScanTile - 1) / kScanTile; }
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of a uint32 array (three passes).
 
-// deg[v] += 1 for every incidence; ids >= n raise PEEL_FLAG_ERANGE and are skipped.
-template <int R>
+// part[b] = sum of in over tile b; pmax[b] (if given) = its maximum.
 __global__ void __launch_bounds__(kBlock)
-    k_count(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t *deg,
-            uint32_t *info) {
-  for (uint64_t e = blockIdx.x * (uint64_t)kBlock + threadIdx.x; e < m;
-       e += (uint64_t)gridDim.x * kBlock) {
-    const uint32_t *row = edges + e * R;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const uint32_t v = row[j];
-      if (v < n)
-        atomicAdd(&deg[v], 1u);
-      else
-        atomicOr(&info[0], PEEL_FLAG_ERANGE);
-    }
-  }
-}
-
-// part[b] = sum of deg over tile b; pmax[b] = its maximum.
-__global__ void __launch_bounds__(kBlock)
-    k_tile_sums(const uint32_t *__restrict__ deg, uint32_t n, uint32_t *part, uint32_t *pmax) {
+    k_scan_tiles(const uint32_t *__restrict__ in, uint64_t count, uint32_t *part, uint32_t *pmax) {
   __shared__ uint32_t lds[kBlock / kWave + 1];
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
   uint32_t s = 0, mx = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const uint64_t v = base + i;
-    if (v < n) {
-      const uint32_t d = deg[v];
+    if (base + i < count) {
+      const uint32_t d = in[base + i];
       s += d;
       mx = d > mx ? d : mx;
     }
   }
   const uint32_t tot = block_sum(s, lds);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
-  const uint32_t bmax = block_max(mx, lds);
-  if (threadIdx.x == 0) pmax[blockIdx.x] = bmax;
+  if (pmax) {
+    const uint32_t bmax = block_max(mx, lds);
+    if (threadIdx.x == 0) pmax[blockIdx.x] = bmax;
+  }
 }
 
-// Exclusive scan of part[0..tiles) in place by one workgroup; offsets[n] =
-// total; info[1] = maximum of pmax.
+// Exclusive scan of part[0..tiles) in place (one workgroup); *total = the sum;
+// *max_out (if given) = maximum of pmax.
 __global__ void __launch_bounds__(kBlock)
-    k_scan_parts(uint32_t *part, const uint32_t *pmax, uint64_t tiles, uint32_t *offsets,
-                 uint32_t n, uint32_t *info) {
+    k_scan_parts(uint32_t *part, const uint32_t *pmax, uint64_t tiles, uint32_t *total,
+                 uint32_t *max_out) {
   __shared__ uint32_t lds[kBlock / kWave + 1];
-  uint32_t carry = 0, mx = 0;
-  for (uint64_t b = threadIdx.x; b < tiles; b += kBlock) mx = pmax[b] > mx ? pmax[b] : mx;
-  mx = block_max(mx, lds);
-  if (threadIdx.x == 0) info[1] = mx;
+  if (max_out) {
+    uint32_t mx = 0;
+    for (uint64_t b = threadIdx.x; b < tiles; b += kBlock) mx = pmax[b] > mx ? pmax[b] : mx;
+    mx = block_max(mx, lds);
+    if (threadIdx.x == 0) *max_out = mx;
+  }
+  uint32_t carry = 0;
   for (uint64_t b0 = 0; b0 < tiles; b0 += (uint64_t)kBlock * kScanItems) {
     const uint64_t base = b0 + (uint64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
@@ -89,31 +89,180 @@ __global__ void __launch_bounds__(kBlock)
     }
     carry += tot;
   }
-  if (threadIdx.x == 0) offsets[n] = carry;
+  if (threadIdx.x == 0 && total) *total = carry;
 }
 
-// offsets[v] = part[tile] + prefix of deg inside the tile; cursor[v] = offsets[v].
+// out[i] = part[tile] + prefix of in inside the tile; out2 (if given) gets a copy.
 __global__ void __launch_bounds__(kBlock)
-    k_tile_scan(const uint32_t *__restrict__ deg, uint32_t n, const uint32_t *__restrict__ part,
-                uint32_t *offsets, uint32_t *cursor) {
+    k_scan_apply(const uint32_t *in, uint64_t count, const uint32_t *__restrict__ part,
+                 uint32_t *out, uint32_t *out2) {
   __shared__ uint32_t lds[kBlock / kWave + 1];
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint32_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < n) ? deg[base + i] : 0u;
+    v[i] = (base + i < count) ? in[base + i] : 0u;
     s += v[i];
   }
   uint32_t tot;
   uint32_t run = part[blockIdx.x] + block_exclusive_scan(s, &tot, lds);
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < n) {
-      offsets[base + i] = run;
-      cursor[base + i] = run;
+    if (base + i < count) {
+      out[base + i] = run;
+      if (out2) out2[base + i] = run;
     }
     run += v[i];
+  }
+}
+
+// Enqueues the exclusive scan of in[0..count) into out (may alias in).
+void scan_u32(const uint32_t *in, uint64_t count, uint32_t *out, uint32_t *out2, uint32_t *part,
+              uint32_t *pmax, uint32_t *total, uint32_t *max_out, hipStream_t s) {
+  const uint64_t tiles = scan_tiles(count);
+  if (tiles == 0) return;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, in, count, part, pmax);
+  hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, s, part, pmax, tiles, total, max_out);
+  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kBlock), 0, s, in, count, part, out, out2);
+}
+
+// *out = maximum of in[0..count) (one workgroup).
+__global__ void __launch_bounds__(kBlock) k_max_u32(const uint32_t *in, uint64_t count, uint32_t *out) {
+  __shared__ uint32_t lds[kBlock / kWave + 1];
+  uint32_t mx = 0;
+  for (uint64_t i = threadIdx.x; i < count; i += kBlock) mx = in[i] > mx ? in[i] : mx;
+  mx = block_max(mx, lds);
+  if (threadIdx.x == 0) *out = mx;
+}
+
+// ---------------------------------------------------------------------------
+// Binned build.
+
+// LDS index with one pad word per 32, so that a thread walking 64 consecutive
+// counters does not hit the same bank as its neighbours.
+__device__ inline uint32_t pad(uint32_t i) { return i + (i >> 5); }
+
+// hist[b * ntiles + tile] = incidences of this edge tile whose vertex is in bucket b.
+template <int R>
+__global__ void __launch_bounds__(kBlock)
+    k_bin_count(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nb,
+                uint64_t ntiles, uint32_t *hist, uint32_t *info) {
+  __shared__ uint32_t h[kMaxBuckets];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) h[b] = 0;
+  __syncthreads();
+  const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
+  const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
+  bool bad = false;
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+    const uint32_t *row = edges + e * R;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint32_t v = row[j];
+      if (v < n)
+        atomicAdd(&h[v >> kBinShift], 1u);
+      else
+        bad = true;
+    }
+  }
+  if (bad) atomicOr(&info[0], PEEL_FLAG_ERANGE);
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) hist[(uint64_t)b * ntiles + blockIdx.x] = h[b];
+}
+
+// pairs[...] = (edge << 32 | vertex) grouped by bucket, each tile in its own slice.
+template <int R>
+__global__ void __launch_bounds__(kBlock)
+    k_bin_scatter(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nb,
+                  uint64_t ntiles, const uint32_t *__restrict__ hist, uint64_t *pairs) {
+  __shared__ uint32_t cur[kMaxBuckets];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) cur[b] = hist[(uint64_t)b * ntiles + blockIdx.x];
+  __syncthreads();
+  const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
+  const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+    const uint32_t *row = edges + e * R;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint32_t v = row[j];
+      if (v < n) {
+        const uint32_t pos = atomicAdd(&cur[v >> kBinShift], 1u);
+        pairs[pos] = (e << 32) | v;
+      }
+    }
+  }
+}
+
+// One workgroup per bucket: degrees, offsets and edge lists of its vertices.
+__global__ void __launch_bounds__(kBlock)
+    k_bin_build(const uint64_t *__restrict__ pairs, uint32_t n, uint32_t nb, uint64_t ntiles,
+                const uint32_t *__restrict__ hist, const uint32_t *total, uint32_t *offsets,
+                uint32_t *inc, uint32_t *deg, uint32_t *pmax) {
+  __shared__ uint32_t cnt[kBinV + kBinV / 32];
+  __shared__ uint32_t lds[kBlock / kWave + 1];
+  const uint32_t b = blockIdx.x;
+  const uint32_t base = hist[(uint64_t)b * ntiles];
+  const uint32_t end = (b + 1 < nb) ? hist[(uint64_t)(b + 1) * ntiles] : *total;
+  const uint32_t v0 = b << kBinShift;
+  const uint32_t nv = (n - v0) < (uint32_t)kBinV ? (n - v0) : (uint32_t)kBinV;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(kBinV + kBinV / 32); i += kBlock) cnt[i] = 0;
+  __syncthreads();
+  for (uint32_t p = base + threadIdx.x; p < end; p += kBlock)
+    atomicAdd(&cnt[pad(static_cast<uint32_t>(pairs[p]) - v0)], 1u);
+  __syncthreads();
+  // exclusive scan of cnt[0..kBinV): 64 consecutive counts per thread
+  constexpr int kPer = kBinV / kBlock;
+  const uint32_t i0 = threadIdx.x * kPer;
+  uint32_t s = 0, mx = 0;
+  for (int i = 0; i < kPer; ++i) {
+    const uint32_t d = cnt[pad(i0 + i)];
+    s += d;
+    mx = d > mx ? d : mx;
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(s, &tot, lds);
+  for (int i = 0; i < kPer; ++i) {
+    const uint32_t v = i0 + i;
+    const uint32_t d = cnt[pad(v)];
+    if (v < nv) {
+      offsets[v0 + v] = base + run;
+      deg[v0 + v] = d;
+    }
+    cnt[pad(v)] = run;  // becomes the cursor
+    run += d;
+  }
+  const uint32_t bmax = block_max(mx, lds);
+  if (threadIdx.x == 0) {
+    pmax[b] = bmax;
+    if (b == nb - 1) offsets[n] = end;
+  }
+  __syncthreads();
+  for (uint32_t p = base + threadIdx.x; p < end; p += kBlock) {
+    const uint64_t pr = pairs[p];
+    const uint32_t pos = atomicAdd(&cnt[pad(static_cast<uint32_t>(pr) - v0)], 1u);
+    inc[base + pos] = static_cast<uint32_t>(pr >> 32);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fallback for n > 2^26: one device atomic per incidence.
+
+// deg[v] += 1 for every incidence; ids >= n raise PEEL_FLAG_ERANGE and are skipped.
+template <int R>
+__global__ void __launch_bounds__(kBlock)
+    k_count(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t *deg,
+            uint32_t *info) {
+  for (uint64_t e = blockIdx.x * (uint64_t)kBlock + threadIdx.x; e < m;
+       e += (uint64_t)gridDim.x * kBlock) {
+    const uint32_t *row = edges + e * R;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint32_t v = row[j];
+      if (v < n)
+        atomicAdd(&deg[v], 1u);
+      else
+        atomicOr(&info[0], PEEL_FLAG_ERANGE);
+    }
   }
 }
 
@@ -136,35 +285,85 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// ---------------------------------------------------------------------------
+struct Sizes {
+  uint64_t ntiles, nb, hist, pairs;
+};
+
+Sizes sizes(uint32_t n, uint64_t m, uint32_t r) {
+  Sizes z{};
+  if (binned(n)) {
+    z.ntiles = ceil_div(m, kTileEdges);
+    z.nb = ceil_div(n, kBinV);
+    z.hist = (z.ntiles ? z.ntiles : 1) * z.nb;
+    z.pairs = m * r;
+  } else {
+    z.hist = (uint64_t)n + 1;  // degrees then cursors
+  }
+  return z;
+}
+
+size_t build_ws_bytes(uint32_t n, uint64_t m, uint32_t r) {
+  const Sizes z = sizes(n, m, r);
+  const uint64_t scan_n = z.hist > n ? z.hist : n;
+  return align_up(z.hist * 4) + 2 * align_up(scan_tiles(scan_n) * 4 + 4) +
+         align_up(z.pairs * 8) + align_up((z.nb + 1) * 4) + 256;
+}
+
 template <int R>
-peel_status launch_edges(bool scatter, const uint32_t *edges, uint64_t m, uint32_t n,
-                         uint32_t *a, uint32_t *b, hipStream_t s) {
-  if (m == 0) return PEEL_OK;
-  const unsigned grid = grid_for(m, kBlock, 1u << 16);
-  if (scatter)
-    hipLaunchKernelGGL(k_scatter<R>, dim3(grid), dim3(kBlock), 0, s, edges, m, n, a, b);
-  else
-    hipLaunchKernelGGL(k_count<R>, dim3(grid), dim3(kBlock), 0, s, edges, m, n, a, b);
+peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t *offsets,
+                         uint32_t *inc, uint32_t *deg, uint32_t *info, Carver &c, hipStream_t s) {
+  const Sizes z = sizes(n, m, R);
+  uint32_t *hist = c.take<uint32_t>(z.hist);
+  uint32_t *part = c.take<uint32_t>(scan_tiles(z.hist) + 1);
+  uint64_t *pairs = c.take<uint64_t>(z.pairs ? z.pairs : 1);
+  uint32_t *pmax = c.take<uint32_t>(z.nb + 1);
+  uint32_t *total = pmax + z.nb;
+  if (z.ntiles) {
+    hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kBlock), 0, s, edges, m, n,
+                       (uint32_t)z.nb, z.ntiles, hist, info);
+    scan_u32(hist, z.hist, hist, nullptr, part, nullptr, total, nullptr, s);
+    hipLaunchKernelGGL(k_bin_scatter<R>, dim3(z.ntiles), dim3(kBlock), 0, s, edges, m, n,
+                       (uint32_t)z.nb, z.ntiles, hist, pairs);
+  } else {
+    // no edges: every bucket is empty
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(z.nb, kBlock, 4096)), dim3(kBlock), 0, s,
+                       hist, z.nb, 0u);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(kBlock), 0, s, total, (uint64_t)1, 0u);
+  }
+  hipLaunchKernelGGL(k_bin_build, dim3(z.nb), dim3(kBlock), 0, s, pairs, n, (uint32_t)z.nb,
+                     z.ntiles ? z.ntiles : 1, hist, total, offsets, inc, deg, pmax);
+  hipLaunchKernelGGL(k_max_u32, dim3(1), dim3(kBlock), 0, s, pmax, z.nb, info + 1);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }
 
-peel_status dispatch_edges(uint32_t r, bool scatter, const uint32_t *edges, uint64_t m,
-                           uint32_t n, uint32_t *a, uint32_t *b, hipStream_t s) {
-  switch (r) {
-    case 2: return launch_edges<2>(scatter, edges, m, n, a, b, s);
-    case 3: return launch_edges<3>(scatter, edges, m, n, a, b, s);
-    case 4: return launch_edges<4>(scatter, edges, m, n, a, b, s);
-    case 5: return launch_edges<5>(scatter, edges, m, n, a, b, s);
-    case 6: return launch_edges<6>(scatter, edges, m, n, a, b, s);
-    case 7: return launch_edges<7>(scatter, edges, m, n, a, b, s);
-    case 8: return launch_edges<8>(scatter, edges, m, n, a, b, s);
-    default: return PEEL_EINVAL;
+template <int R>
+peel_status build_atomic(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t *offsets,
+                         uint32_t *inc, uint32_t *deg, uint32_t *info, Carver &c, hipStream_t s) {
+  uint32_t *cursor = c.take<uint32_t>((uint64_t)n + 1);
+  uint32_t *part = c.take<uint32_t>(scan_tiles(n) + 1);
+  uint32_t *pmax = c.take<uint32_t>(scan_tiles(n) + 1);
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s,
+                     deg, (uint64_t)n, 0u);
+  if (m) {
+    hipLaunchKernelGGL(k_count<R>, dim3(grid_for(m, kBlock, 1u << 16)), dim3(kBlock), 0, s,
+                       edges, m, n, deg, info);
   }
+  scan_u32(deg, n, offsets, cursor, part, pmax, offsets + n, info + 1, s);
+  if (m) {
+    hipLaunchKernelGGL(k_scatter<R>, dim3(grid_for(m, kBlock, 1u << 16)), dim3(kBlock), 0, s,
+                       edges, m, n, cursor, inc);
+  }
+  PEEL_HIP_TRY(hipGetLastError());
+  return PEEL_OK;
 }
 
-size_t build_ws_bytes(uint32_t n) {
-  return align_up((size_t)n * 4) + 2 * align_up(scan_tiles(n) * 4) + 256;
+template <int R>
+peel_status build(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t *offsets, uint32_t *inc,
+                  uint32_t *deg, uint32_t *info, Carver &c, hipStream_t s) {
+  return binned(n) ? build_binned<R>(edges, m, n, offsets, inc, deg, info, c, s)
+                   : build_atomic<R>(edges, m, n, offsets, inc, deg, info, c, s);
 }
 
 }  // namespace
@@ -173,9 +372,7 @@ size_t build_ws_bytes(uint32_t n) {
 using namespace peel;
 
 extern "C" size_t hg_build_workspace(uint32_t n, uint64_t m, uint32_t r) {
-  (void)m;
-  (void)r;
-  return build_ws_bytes(n);
+  return build_ws_bytes(n, m, r);
 }
 
 extern "C" peel_status hg_build(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n,
@@ -184,23 +381,18 @@ extern "C" peel_status hg_build(const uint32_t *edges, uint64_t m, uint32_t r, u
   if (r < 2 || r > 8 || n == 0) return PEEL_EINVAL;
   if (m * (uint64_t)r >= (1ull << 32)) return PEEL_EINVAL;
   if ((m && (!edges || !inc)) || !offsets || !deg || !info || !ws) return PEEL_EINVAL;
-  if (ws_bytes < build_ws_bytes(n)) return PEEL_ENOSPC;
+  if (ws_bytes < build_ws_bytes(n, m, r)) return PEEL_ENOSPC;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Carver c(ws);
-  BuildWs w{c.take<uint32_t>(n), c.take<uint32_t>(scan_tiles(n)), c.take<uint32_t>(scan_tiles(n))};
-  const uint64_t tiles = scan_tiles(n);
-
-  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s,
-                     deg, (uint64_t)n, 0u);
   hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(kBlock), 0, s, info, (uint64_t)2, 0u);
   PEEL_HIP_TRY(hipGetLastError());
-  peel_status st = dispatch_edges(r, false, edges, m, n, deg, info, s);
-  if (st) return st;
-  hipLaunchKernelGGL(k_tile_sums, dim3(tiles), dim3(kBlock), 0, s, deg, n, w.part, w.pmax);
-  hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, s, w.part, w.pmax, tiles, offsets,
-                     n, info);
-  hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, deg, n, w.part, offsets,
-                     w.cursor);
-  PEEL_HIP_TRY(hipGetLastError());
-  return dispatch_edges(r, true, edges, m, n, w.cursor, inc, s);
+  switch (r) {
+    case 2: return build<2>(edges, m, n, offsets, inc, deg, info, c, s);
+    case 3: return build<3>(edges, m, n, offsets, inc, deg, info, c, s);
+    case 4: return build<4>(edges, m, n, offsets, inc, deg, info, c, s);
+    case 5: return build<5>(edges, m, n, offsets, inc, deg, info, c, s);
+    case 6: return build<6>(edges, m, n, offsets, inc, deg, info, c, s);
+    case 7: return build<7>(edges, m, n, offsets, inc, deg, info, c, s);
+    default: return build<8>(edges, m, n, offsets, inc, deg, info, c, s);
+  }
 }

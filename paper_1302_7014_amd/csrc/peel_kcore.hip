@@ -4,29 +4,47 @@
 // below k at the start of the round is removed at once, together with every
 // edge still holding it; the run ends at the first round with nothing to
 // remove.  Section 5 ("Implementation Details") notes that a parallel peel
-// must never peel one edge twice; here the edge's round word is claimed by
-// compare-and-swap (0 -> t), so exactly one of the peeled vertices that share
-// an edge removes it.
+// must never peel one edge twice.
 //
-// One persistent kernel (a run-time team of resident workgroups) runs every round, with a
-// device-wide barrier between rounds and no host round trip:
-//   phase 0   dense pass: zero edge rounds and stats, mark vertex_round = 1 and
-//             compact F_1 = {v : deg(v) < k} (block prefix sum, one atomic per
-//             2048-vertex tile, so F_1 comes out in ascending tiles);
-//   round t   for v in F_t and each incidence e of v still alive: CAS the
-//             edge's round word 0 -> t; the winner lowers the degree of each of
-//             e's r slots.  A decrement that takes a degree from k to k-1
-//             marks that vertex for round t+1 (vertex_round = t+1) and pushes
-//             it onto F_{t+1} through a per-workgroup LDS queue.
+// Two engines, both persistent kernels whose team of resident workgroups is
+// formed at run time, with no host round trip between rounds:
 //
-// Why this is exact: a vertex alive at the start of round t with degree >= k
+// Owner engine (the default).  Device-scope atomics run at a fixed ~27 G/s on
+// this GPU whatever the working set, so the owner engine keeps the per-edge
+// work in LDS.  Each of T workgroups (one per CU) owns a range of Vb vertices,
+// whose degrees it holds as bytes in LDS, and a range of Eb edges, whose
+// "alive" bits it holds in LDS.  A round is two message exchanges through
+// per-destination queues in HBM (a workgroup counts its messages per
+// destination in LDS, reserves space with one atomic per destination, then
+// writes them):
+//   claims      each owner sends, for every vertex of its frontier F_t, one
+//               claim per incident edge to that edge's owner;
+//   decrements  each edge owner clears the alive bit of every claimed edge
+//               (an LDS atomic, so an edge claimed by several peeled vertices
+//               dies once), stamps its round, and sends one decrement per slot
+//               to the slot vertex's owner, which lowers the LDS degree; a
+//               decrement that takes a degree from k to k-1 puts the vertex
+//               into the owner's F_{t+1}.
+// A hierarchical barrier after each exchange also sums |F_t| and the edges
+// removed.  A degree >= 255 lives in the global degree array instead (marked
+// 255 in LDS) and is updated with device atomics.
+//
+// Global engine (used when a workgroup's vertex or edge range does not fit in
+// LDS, or the team is too small).  Every round, the threads walk F_t and claim
+// each still-alive incident edge by compare-and-swap on its round word
+// (0 -> t); the winner lowers the degree of each of its r slots with a device
+// atomic and pushes a vertex whose degree crossed k -> k-1 onto F_{t+1}.
+//
+// Both are exact: a vertex alive at the start of round t with degree >= k
 // crosses k -> k-1 at most once, so F_{t+1} is exactly the set of alive
 // vertices whose degree dropped below k during round t; vertices of F_t start
 // below k and never trigger a push.  Every slot of a removed edge is
 // decremented, so removed vertices end at degree 0 and core vertices at their
-// core degree, independent of which thread wins a CAS.
+// core degree, whatever the order of the atomics.
 #include "common.hpp"
 #include "host.hpp"
+
+#include <cstring>
 
 namespace peel {
 namespace {
@@ -34,19 +52,32 @@ namespace {
 #ifndef PEEL_LDS_QUEUE
 #define PEEL_LDS_QUEUE 4096
 #endif
-constexpr int kQueue = PEEL_LDS_QUEUE;          // LDS push-queue entries per workgroup
-constexpr int kDenseItems = 8;        // vertices per thread in the dense pass
+constexpr int kQueue = PEEL_LDS_QUEUE;  // LDS push-queue entries per workgroup (global engine)
+constexpr int kDenseItems = 8;          // vertices per thread in the dense pass
 constexpr int kDenseTile = kBlock * kDenseItems;
 
+constexpr int kOT = 1024;             // threads per owner workgroup
+constexpr uint32_t kOwnMaxV = 98304;  // owned vertices (LDS degree bytes)
+constexpr uint32_t kOwnMaxE = 131072; // owned edges (LDS alive bits)
+constexpr uint32_t kOwnMaxT = 1024;   // owner workgroups (LDS per-destination counters)
+
+enum : uint32_t { kModeUndecided = 0, kModeOwnerDone = 1, kModeGlobal = 2 };
+
 struct PeelCtrl {
-  GridSync sync;
-  Team team;
-  uint32_t fcount[3];  // |F_t| lives in fcount[t % 3]
+  SumBar bar;          // owner engine barrier
+  GridSync sync;       // global engine barrier
+  Team team_own;
+  Team team_glob;
+  uint32_t mode;
+  uint32_t fcount[3];  // global engine: |F_t| lives in fcount[t % 3]
   uint32_t flags;
   uint32_t rounds;
+  uint32_t team;
   uint32_t pad;
   uint64_t removed;
-  uint64_t stamp[256];  // wall clock at each barrier generation (diagnostic)
+  uint32_t qh_claim[kOwnMaxT];  // owner engine queue heads
+  uint32_t qh_dec[kOwnMaxT];
+  uint64_t stamp[256];          // wall clock at each barrier generation (diagnostic)
 };
 
 struct PeelArgs {
@@ -57,8 +88,11 @@ struct PeelArgs {
   uint32_t *vr;
   uint32_t *er;
   uint64_t *stats;
-  uint32_t *fa;
+  uint32_t *fa;      // frontiers (n each)
   uint32_t *fb;
+  uint32_t *qclaim;  // owner engine: R * (m + grid) claim slots
+  uint32_t *qdec;    // owner engine: R * m decrement slots, laid out by the CSR offsets
+  uint32_t *stage;   // owner engine: R * (m + grid) rows of the edges won this round
   PeelCtrl *ctrl;
   uint64_t m;
   uint64_t limit;
@@ -66,23 +100,199 @@ struct PeelArgs {
   uint32_t n;
   uint32_t k;
   uint32_t max_rounds;
+  uint32_t force_global;  // PEEL_ENGINE=global: skip the owner engine (testing)
 };
 
 __global__ void k_peel_init(PeelCtrl *ctrl) {
-  if (threadIdx.x == 0) {
-    ctrl->sync.count = 0;
-    ctrl->sync.gen = 0;
-    ctrl->sync.abort = 0;
-    ctrl->sync.pad = 0;
-    ctrl->team.join = 0;
-    ctrl->team.size = 0;
-    ctrl->fcount[0] = ctrl->fcount[1] = ctrl->fcount[2] = 0;
-    ctrl->flags = 0;
-    ctrl->rounds = 0;
-    ctrl->pad = 0;
-    ctrl->removed = 0;
+  uint32_t *w = reinterpret_cast<uint32_t *>(ctrl);
+  for (uint32_t i = threadIdx.x; i < sizeof(PeelCtrl) / 4; i += blockDim.x) w[i] = 0;
+}
+
+// ===========================================================================
+// Owner engine.
+
+template <int R>
+__global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
+  __shared__ uint32_t deg8[kOwnMaxV / 4];  // 4 degree bytes per word
+  __shared__ uint32_t alive[kOwnMaxE / 32];
+  __shared__ uint32_t cnt[kOwnMaxT];
+  __shared__ uint32_t cur[kOwnMaxT];
+  __shared__ uint32_t s_n, s_w;
+
+  PeelCtrl *ctrl = a.ctrl;
+  uint32_t slot, T;
+  if (!team_join(&ctrl->team_own, a.quiet, a.limit, &slot, &T)) return;
+  const uint32_t n = a.n;
+  const uint32_t Vb = (n + T - 1) / T;
+  const uint64_t m = a.m;
+  const uint32_t Eb = m ? (uint32_t)((m + T - 1) / T) : 1u;
+  if (a.force_global || T > kOwnMaxT || Vb > kOwnMaxV || Eb > kOwnMaxE) {
+    if (slot == 0 && threadIdx.x == 0) ctrl->mode = kModeGlobal;
+    return;
+  }
+  const uint32_t tid = threadIdx.x;
+  const uint32_t v0 = slot * Vb < n ? slot * Vb : n;
+  const uint32_t v1 = v0 + Vb < n ? v0 + Vb : n;
+  const uint64_t e0 = (uint64_t)slot * Eb < m ? (uint64_t)slot * Eb : m;
+  const uint64_t e1 = e0 + Eb < m ? e0 + Eb : m;
+  const uint32_t k = a.k;
+  uint32_t *myF = a.fa + v0;
+  uint32_t *myStage = a.stage + (uint64_t)slot * Eb * R;
+  const uint32_t *myClaims = a.qclaim + (uint64_t)slot * Eb * R;
+  const uint32_t *myDecs = a.qdec + a.offsets[v0];
+
+  // ---- init: LDS degrees, alive bits, outputs, F_1 --------------------------
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  for (uint32_t w = tid; w < (Vb + 3) / 4; w += kOT) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t v = v0 + 4 * w + i;
+      if (v < v1) {
+        const uint32_t d = a.deg[v];
+        word |= (d >= 255u ? 255u : d) << (8 * i);
+        a.vr[v] = 0;
+        if (d < k) myF[atomicAdd(&s_n, 1u)] = v;
+      }
+    }
+    deg8[w] = word;
+  }
+  for (uint32_t w = tid; w < (Eb + 31) / 32; w += kOT) {
+    const uint64_t lo = e0 + 32ull * w;
+    uint32_t bits = 0;
+    if (lo < e1) bits = (e1 - lo >= 32) ? 0xffffffffu : ((1u << (uint32_t)(e1 - lo)) - 1u);
+    alive[w] = bits;
+  }
+  for (uint64_t e = e0 + tid; e < e1; e += kOT) a.er[e] = 0;
+  if (slot == 0)
+    for (uint64_t i = tid; i < 2ull * a.max_rounds; i += kOT) a.stats[i] = 0;
+  __syncthreads();
+  uint32_t fcnt = s_n;
+
+  uint32_t epoch = 0;
+  uint64_t removed = 0;
+  uint32_t t = 1;
+  for (;; ++t) {
+    // ---- claims: one per incidence of every vertex of F_t --------------------
+    const bool over = t > a.max_rounds;
+    if (!over) {
+      for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
+      __syncthreads();
+      for (uint32_t i = tid; i < fcnt; i += kOT) {
+        const uint32_t v = myF[i];
+        a.vr[v] = t;
+        const uint32_t p1 = a.offsets[v + 1];
+        for (uint32_t p = a.offsets[v]; p < p1; ++p) atomicAdd(&cnt[a.inc[p] / Eb], 1u);
+      }
+      __syncthreads();
+      for (uint32_t d = tid; d < T; d += kOT) {
+        const uint32_t c = cnt[d];
+        cur[d] = c ? d * Eb * R + atomicAdd(&ctrl->qh_claim[d], c) : 0u;
+      }
+      __syncthreads();
+      for (uint32_t i = tid; i < fcnt; i += kOT) {
+        const uint32_t v = myF[i];
+        const uint32_t p1 = a.offsets[v + 1];
+        for (uint32_t p = a.offsets[v]; p < p1; ++p) {
+          const uint32_t e = a.inc[p];
+          a.qclaim[atomicAdd(&cur[e / Eb], 1u)] = e;
+        }
+      }
+    }
+    uint64_t vt;
+    if (!sum_barrier(&ctrl->bar, T, slot, fcnt, &epoch, a.limit, &vt, ctrl->stamp)) return;
+    if (vt == 0) break;
+    if (over) {
+      // F_t stays in the graph: the outputs hold the state after max_rounds rounds.
+      if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_EROUNDS);
+      break;
+    }
+    removed += vt;
+    if (slot == 0 && tid == 0) a.stats[2ull * (t - 1)] = vt;
+
+    // ---- edge owners: claimed edges die once; decrements to every slot -------
+    if (tid == 0) {
+      s_n = ctrl->qh_claim[slot];
+      ctrl->qh_claim[slot] = 0;
+      s_w = 0;
+    }
+    for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
+    __syncthreads();
+    const uint32_t nclaims = s_n;
+    for (uint32_t i = tid; i < nclaims; i += kOT) {
+      const uint32_t e = myClaims[i];
+      const uint32_t le = e - (uint32_t)e0;
+      const uint32_t bit = 1u << (le & 31);
+      if (atomicAnd(&alive[le >> 5], ~bit) & bit) {
+        a.er[e] = t;
+        const uint32_t w = atomicAdd(&s_w, 1u);
+        const uint32_t *row = a.edges + (uint64_t)e * R;
+        uint32_t ids[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) ids[j] = row[j];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          myStage[(uint64_t)w * R + j] = ids[j];
+          if (ids[j] < n) atomicAdd(&cnt[ids[j] / Vb], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t won = s_w;
+    for (uint32_t d = tid; d < T; d += kOT) {
+      const uint32_t c = cnt[d];
+      const uint32_t dv = d * Vb < n ? d * Vb : n;
+      cur[d] = c ? a.offsets[dv] + atomicAdd(&ctrl->qh_dec[d], c) : 0u;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < won * R; i += kOT) {
+      const uint32_t u = myStage[i];
+      if (u < n) a.qdec[atomicAdd(&cur[u / Vb], 1u)] = u;
+    }
+    uint64_t et;
+    if (!sum_barrier(&ctrl->bar, T, slot, won, &epoch, a.limit, &et, ctrl->stamp)) return;
+    if (slot == 0 && tid == 0) a.stats[2ull * (t - 1) + 1] = et;
+
+    // ---- vertex owners: apply decrements, collect F_{t+1} --------------------
+    if (tid == 0) {
+      s_w = ctrl->qh_dec[slot];
+      ctrl->qh_dec[slot] = 0;
+      s_n = 0;
+    }
+    __syncthreads();
+    const uint32_t ndec = s_w;
+    for (uint32_t i = tid; i < ndec; i += kOT) {
+      const uint32_t u = myDecs[i];
+      const uint32_t lv = u - v0;
+      const uint32_t sh = 8 * (lv & 3);
+      uint32_t old;
+      if (((deg8[lv >> 2] >> sh) & 255u) == 255u)
+        old = atomicSub(&a.deg[u], 1u);
+      else
+        old = (atomicSub(&deg8[lv >> 2], 1u << sh) >> sh) & 255u;
+      if (old == k) myF[atomicAdd(&s_n, 1u)] = u;
+    }
+    __syncthreads();
+    fcnt = s_n;
+  }
+
+  // ---- epilogue: final degrees of the vertices kept in LDS --------------------
+  for (uint32_t v = v0 + tid; v < v1; v += kOT) {
+    const uint32_t lv = v - v0;
+    const uint32_t d = (deg8[lv >> 2] >> (8 * (lv & 3))) & 255u;
+    if (d != 255u) a.deg[v] = d;
+  }
+  if (slot == 0 && tid == 0) {
+    ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
+    ctrl->removed = removed;
+    ctrl->team = T;
+    ctrl->mode = kModeOwnerDone;
   }
 }
+
+// ===========================================================================
+// Global engine.
 
 template <int R>
 __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
@@ -92,16 +302,18 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
   __shared__ uint32_t lds[kBlock / kWave + 1];
 
   PeelCtrl *ctrl = a.ctrl;
+  // Runs only when the owner engine declined this input.
+  if (__hip_atomic_load(&ctrl->mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kModeGlobal)
+    return;
   uint32_t slot, nblocks;
-  if (!team_join(&ctrl->team, a.quiet, a.limit, &slot, &nblocks)) return;
+  if (!team_join(&ctrl->team_glob, a.quiet, a.limit, &slot, &nblocks)) return;
   const uint64_t gtid = (uint64_t)slot * kBlock + threadIdx.x;
   const uint64_t gsize = (uint64_t)nblocks * kBlock;
 
   // ---- phase 0 ------------------------------------------------------------
   for (uint64_t e = gtid; e < a.m; e += gsize) a.er[e] = 0;
   for (uint64_t i = gtid; i < 2ull * a.max_rounds; i += gsize) a.stats[i] = 0;
-  for (uint64_t t0 = (uint64_t)slot * kDenseTile; t0 < a.n;
-       t0 += (uint64_t)nblocks * kDenseTile) {
+  for (uint64_t t0 = (uint64_t)slot * kDenseTile; t0 < a.n; t0 += (uint64_t)nblocks * kDenseTile) {
     const uint64_t base = t0 + (uint64_t)threadIdx.x * kDenseItems;
     uint32_t low = 0, cnt = 0;
 #pragma unroll
@@ -172,9 +384,9 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
           const uint32_t old = atomicSub(&a.deg[u], 1u);
           if (old == a.k) {
             a.vr[u] = t + 1;
-            const uint32_t slot = atomicAdd(&qn, 1u);
-            if (slot < kQueue) {
-              q[slot] = u;
+            const uint32_t slotq = atomicAdd(&qn, 1u);
+            if (slotq < kQueue) {
+              q[slotq] = u;
             } else {
               nxt[atomicAdd(ncount, 1u)] = u;
             }
@@ -194,6 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
   if (gtid == 0) {
     ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
     ctrl->removed = removed;
+    ctrl->team = nblocks;
   }
 }
 
@@ -210,19 +423,42 @@ __global__ void k_peel_finish(const PeelCtrl *ctrl, const uint64_t *stats, uint3
       break;
     }
   uint32_t flags = ctrl->flags;
-  if (ctrl->sync.abort) flags |= PEEL_FLAG_TIMEOUT;
+  if (ctrl->sync.abort || ctrl->bar.abort || ctrl->mode == kModeUndecided)
+    flags |= PEEL_FLAG_TIMEOUT;
   summary[0] = rounds;
   summary[1] = last_e;
   summary[2] = flags;
   summary[3] = static_cast<uint32_t>(n - ctrl->removed);
-  summary[4] = ctrl->team.size;
+  summary[4] = ctrl->team;
   summary[5] = summary[6] = summary[7] = 0;
 }
 
-size_t peel_ws_bytes(uint32_t n) { return align_up(sizeof(PeelCtrl)) + 2 * align_up((size_t)n * 4); }
+struct Layout {
+  size_t ctrl, fa, fb, qclaim, qdec, stage, total;
+};
+
+Layout layout(uint32_t n, uint64_t m, uint32_t r) {
+  const uint64_t g = (uint64_t)device_info().cus + 64;  // owner grid upper bound
+  Layout L{};
+  L.ctrl = align_up(sizeof(PeelCtrl));
+  L.fa = align_up((size_t)n * 4);
+  L.fb = align_up((size_t)n * 4);
+  L.qclaim = align_up((size_t)r * (m + g) * 4);
+  L.qdec = align_up((size_t)r * m * 4 + 4);
+  L.stage = align_up((size_t)r * (m + g) * 4);
+  L.total = L.ctrl + L.fa + L.fb + L.qclaim + L.qdec + L.stage;
+  return L;
+}
 
 template <int R>
 peel_status launch(PeelArgs &a, hipStream_t s) {
+  const DeviceInfo &dev = device_info();
+  // owner engine: one workgroup per CU (its LDS use allows no more)
+  const unsigned og = static_cast<unsigned>(dev.cus < (int)kOwnMaxT ? dev.cus : (int)kOwnMaxT);
+  if (dev.debug) std::fprintf(stderr, "[peel] owner grid %u\n", og);
+  hipLaunchKernelGGL(k_peel_owner<R>, dim3(og), dim3(kOT), 0, s, a);
+  PEEL_HIP_TRY(hipGetLastError());
+  // global engine: runs only if the owner engine declined
   const void *fn = reinterpret_cast<const void *>(&k_peel_persistent<R>);
   const int cap = coresident_blocks(fn, kBlock, 0);
   uint64_t want = ((uint64_t)a.n + kDenseTile - 1) / kDenseTile;
@@ -230,8 +466,7 @@ peel_status launch(PeelArgs &a, hipStream_t s) {
   if (want_m > want) want = want_m;
   if (want < 1) want = 1;
   const unsigned grid = static_cast<unsigned>(want < (uint64_t)cap ? want : (uint64_t)cap);
-  if (device_info().debug) std::fprintf(stderr, "[peel] persistent grid %u (cap %d)\n", grid, cap);
-  // A plain launch: the kernel forms its team of resident workgroups itself.
+  if (dev.debug) std::fprintf(stderr, "[peel] global grid %u (cap %d)\n", grid, cap);
   hipLaunchKernelGGL(k_peel_persistent<R>, dim3(grid), dim3(kBlock), 0, s, a);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
@@ -243,9 +478,7 @@ peel_status launch(PeelArgs &a, hipStream_t s) {
 using namespace peel;
 
 extern "C" size_t peel_kcore_workspace(uint32_t n, uint64_t m, uint32_t r) {
-  (void)m;
-  (void)r;
-  return peel_ws_bytes(n);
+  return layout(n, m, r).total;
 }
 
 extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n,
@@ -258,13 +491,22 @@ extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r,
   if ((m && (!edges || !inc || !edge_round)) || !offsets || !deg || !vertex_round ||
       !round_stats || !summary || !ws)
     return PEEL_EINVAL;
-  if (ws_bytes < peel_ws_bytes(n)) return PEEL_ENOSPC;
+  const Layout L = layout(n, m, r);
+  if (ws_bytes < L.total) return PEEL_ENOSPC;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Carver c(ws);
+  char *base = static_cast<char *>(ws);
   PeelArgs a;
-  a.ctrl = c.take<PeelCtrl>(1);
-  a.fa = c.take<uint32_t>(n);
-  a.fb = c.take<uint32_t>(n);
+  a.ctrl = reinterpret_cast<PeelCtrl *>(base);
+  base += L.ctrl;
+  a.fa = reinterpret_cast<uint32_t *>(base);
+  base += L.fa;
+  a.fb = reinterpret_cast<uint32_t *>(base);
+  base += L.fb;
+  a.qclaim = reinterpret_cast<uint32_t *>(base);
+  base += L.qclaim;
+  a.qdec = reinterpret_cast<uint32_t *>(base);
+  base += L.qdec;
+  a.stage = reinterpret_cast<uint32_t *>(base);
   a.edges = edges;
   a.offsets = offsets;
   a.inc = inc;
@@ -278,8 +520,10 @@ extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r,
   a.max_rounds = max_rounds;
   a.limit = device_info().barrier_limit_ticks;
   a.quiet = device_info().team_quiet_ticks;
+  const char *engine = std::getenv("PEEL_ENGINE");
+  a.force_global = (engine && std::strcmp(engine, "global") == 0) ? 1u : 0u;
 
-  hipLaunchKernelGGL(k_peel_init, dim3(1), dim3(64), 0, s, a.ctrl);
+  hipLaunchKernelGGL(k_peel_init, dim3(1), dim3(256), 0, s, a.ctrl);
   PEEL_HIP_TRY(hipGetLastError());
   peel_status st;
   switch (r) {
