@@ -152,6 +152,9 @@ typedef struct iblt_desc {
 } iblt_desc;
 
 /*
+ * Tables are 32-byte aligned (as torch and hipMalloc allocations are);
+ * calls with a misaligned table return PEEL_EINVAL.
+ *
  * Insert keys: for each key x and each subtable j, count += 1,
  * key_sum ^= x, hash_sum ^= C(x) in x's cell of subtable j (Section 5,
  * "Motivation").  Accumulates into `cells` (device, ncells entries), which
@@ -187,6 +190,37 @@ size_t iblt_list_workspace(const iblt_desc *desc);
 peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
                       uint64_t out_cap, uint64_t *round_stats, uint32_t max_rounds,
                       uint64_t *summary, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched listing (many independent tables in one launch).                   */
+/*
+ * Not in the paper, which lists one table.  Each table is listed exactly as
+ * iblt_list lists it (same rounds, same per-round key sets, same summary),
+ * but all tables run in one kernel launch: workgroups take tables in the
+ * order of `entries` from a shared counter and list each with workgroup-wide
+ * barriers only.  Sorting `entries` by decreasing ncells balances the load.
+ *
+ *   entries       (device) ntables descriptors; every pointer in them is
+ *                 device memory and every table is disjoint from the others.
+ *   max_cells     >= the largest ncells among the tables.
+ *   max_rounds    >= 1, for every table (round_stats hold max_rounds each).
+ *   block_threads 256, 512 or 1024 threads per workgroup; 0 = 512.
+ *   ws            (device) ws_bytes >= iblt_list_batched_workspace().
+ * Each table's summary is written as iblt_list's ([4] = 1 workgroup).
+ */
+typedef struct iblt_batch_entry {
+    iblt_desc desc;
+    iblt_cell *cells;      /* ncells cells, 32-byte aligned, consumed in place */
+    uint64_t *out_keys;    /* out_cap entries                                  */
+    uint64_t out_cap;
+    uint64_t *round_stats; /* max_rounds entries                               */
+    uint64_t *summary;     /* 8 entries                                        */
+} iblt_batch_entry;
+
+size_t iblt_list_batched_workspace(uint32_t ntables, uint64_t max_cells);
+peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32_t ntables,
+                              uint64_t max_cells, uint32_t max_rounds, uint32_t block_threads,
+                              void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,8 @@ FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT = 0x1, 0x2, 
 
 # Every symbol include/peel.h declares.
 EXPORTS = ("peel_strerror", "peel_abi_version", "hg_build_workspace", "hg_build",
-           "peel_kcore_workspace", "peel_kcore", "iblt_insert", "iblt_list_workspace", "iblt_list")
+           "peel_kcore_workspace", "peel_kcore", "iblt_insert", "iblt_list_workspace", "iblt_list",
+           "iblt_list_batched_workspace", "iblt_list_batched")
 
 _lib = None
 
@@ -62,7 +63,10 @@ def lib() -> C.CDLL:
         L.iblt_list_workspace.argtypes = [C.POINTER(IbltDesc)]
         L.iblt_list_workspace.restype = sz
         L.iblt_list.argtypes = [C.POINTER(IbltDesc), P, P, u64, P, u32, P, P, sz, P]
-        for f in ("hg_build", "peel_kcore", "iblt_insert", "iblt_list"):
+        L.iblt_list_batched_workspace.argtypes = [u32, u64]
+        L.iblt_list_batched_workspace.restype = sz
+        L.iblt_list_batched.argtypes = [P, u32, u64, u32, u32, P, sz, P]
+        for f in ("hg_build", "peel_kcore", "iblt_insert", "iblt_list", "iblt_list_batched"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -201,3 +205,53 @@ def iblt_list(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = None,
                            max_rounds, _ptr(out.summary), _ptr(ws), ws.numel(), _stream(stream)),
            "iblt_list")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batched listing.
+
+BATCH_ENTRY = [("ncells", "<u8"), ("r", "<u4"), ("reserved", "<u4"), ("seed", "<u8"),
+               ("cells", "<u8"), ("out_keys", "<u8"), ("out_cap", "<u8"),
+               ("round_stats", "<u8"), ("summary", "<u8")]
+
+
+@dataclass
+class BatchTable:
+    """One table of a batch: its descriptor and device buffers."""
+    desc: IbltDesc
+    cells: torch.Tensor        # (ncells, 4) int64
+    keys: torch.Tensor         # int64[out_cap]
+    round_stats: torch.Tensor  # int64[max_rounds]
+    summary: torch.Tensor      # int64[8]
+
+
+def batch_table(desc: IbltDesc, cells: torch.Tensor, max_rounds: int,
+                out_cap: int | None = None) -> BatchTable:
+    dev = cells.device
+    cap = desc.ncells if out_cap is None else out_cap
+    return BatchTable(desc, cells, _empty(cap, torch.int64, dev),
+                      _empty(max_rounds, torch.int64, dev), _empty(8, torch.int64, dev))
+
+
+def batch_entries(tables: list[BatchTable], device) -> torch.Tensor:
+    """Device array of iblt_batch_entry (64 bytes each) for ``tables``, in order."""
+    import numpy as np
+    arr = np.zeros(len(tables), dtype=np.dtype(BATCH_ENTRY))
+    for i, t in enumerate(tables):
+        arr[i] = (t.desc.ncells, t.desc.r, 0, t.desc.seed, t.cells.data_ptr(), t.keys.data_ptr(),
+                  t.keys.numel(), t.round_stats.data_ptr(), t.summary.data_ptr())
+    host = torch.from_numpy(arr.view(np.uint8).copy())
+    return host.to(device)
+
+
+def iblt_list_batched_workspace(ntables: int, max_cells: int) -> int:
+    return int(lib().iblt_list_batched_workspace(ntables, max_cells))
+
+
+def iblt_list_batched(entries: torch.Tensor, ntables: int, max_cells: int, max_rounds: int,
+                      block_threads: int = 0, ws: torch.Tensor | None = None, stream=None) -> None:
+    """List every table of a batch in one launch (entries from ``batch_entries``)."""
+    if ws is None:
+        ws = workspace(iblt_list_batched_workspace(ntables, max_cells), entries.device)
+    _check(lib().iblt_list_batched(_ptr(entries), ntables, max_cells, max_rounds, block_threads,
+                                   _ptr(ws), ws.numel(), _stream(stream)), "iblt_list_batched")

@@ -28,6 +28,7 @@ constexpr int kBinShift = 14;                   // 16384 vertices per bucket
 constexpr int kBinV = 1 << kBinShift;
 constexpr int kMaxBuckets = 4096;
 constexpr uint64_t kTileEdges = 16384;          // edges per bin tile
+constexpr int kBT = 1024;                       // threads per workgroup in the bin kernels
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint64_t scan_tiles(uint64_t count) { return ceil_div(count, kScanTile); }
@@ -145,16 +146,16 @@ __device__ inline uint32_t pad(uint32_t i) { return i + (i >> 5); }
 
 // hist[b * ntiles + tile] = incidences of this edge tile whose vertex is in bucket b.
 template <int R>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBT)
     k_bin_count(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nb,
                 uint64_t ntiles, uint32_t *hist, uint32_t *info) {
   __shared__ uint32_t h[kMaxBuckets];
-  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) h[b] = 0;
+  for (uint32_t b = threadIdx.x; b < nb; b += kBT) h[b] = 0;
   __syncthreads();
   const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
   bool bad = false;
-  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBT) {
     const uint32_t *row = edges + e * R;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -167,20 +168,20 @@ __global__ void __launch_bounds__(kBlock)
   }
   if (bad) atomicOr(&info[0], PEEL_FLAG_ERANGE);
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) hist[(uint64_t)b * ntiles + blockIdx.x] = h[b];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBT) hist[(uint64_t)b * ntiles + blockIdx.x] = h[b];
 }
 
 // pairs[...] = (edge << 32 | vertex) grouped by bucket, each tile in its own slice.
 template <int R>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBT)
     k_bin_scatter(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nb,
                   uint64_t ntiles, const uint32_t *__restrict__ hist, uint64_t *pairs) {
   __shared__ uint32_t cur[kMaxBuckets];
-  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) cur[b] = hist[(uint64_t)b * ntiles + blockIdx.x];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBT) cur[b] = hist[(uint64_t)b * ntiles + blockIdx.x];
   __syncthreads();
   const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
-  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBT) {
     const uint32_t *row = edges + e * R;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -194,24 +195,24 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // One workgroup per bucket: degrees, offsets and edge lists of its vertices.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBT)
     k_bin_build(const uint64_t *__restrict__ pairs, uint32_t n, uint32_t nb, uint64_t ntiles,
                 const uint32_t *__restrict__ hist, const uint32_t *total, uint32_t *offsets,
                 uint32_t *inc, uint32_t *deg, uint32_t *pmax) {
   __shared__ uint32_t cnt[kBinV + kBinV / 32];
-  __shared__ uint32_t lds[kBlock / kWave + 1];
+  __shared__ uint32_t lds[kBT / kWave + 1];
   const uint32_t b = blockIdx.x;
   const uint32_t base = hist[(uint64_t)b * ntiles];
   const uint32_t end = (b + 1 < nb) ? hist[(uint64_t)(b + 1) * ntiles] : *total;
   const uint32_t v0 = b << kBinShift;
   const uint32_t nv = (n - v0) < (uint32_t)kBinV ? (n - v0) : (uint32_t)kBinV;
-  for (uint32_t i = threadIdx.x; i < (uint32_t)(kBinV + kBinV / 32); i += kBlock) cnt[i] = 0;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(kBinV + kBinV / 32); i += kBT) cnt[i] = 0;
   __syncthreads();
-  for (uint32_t p = base + threadIdx.x; p < end; p += kBlock)
+  for (uint32_t p = base + threadIdx.x; p < end; p += kBT)
     atomicAdd(&cnt[pad(static_cast<uint32_t>(pairs[p]) - v0)], 1u);
   __syncthreads();
-  // exclusive scan of cnt[0..kBinV): 64 consecutive counts per thread
-  constexpr int kPer = kBinV / kBlock;
+  // exclusive scan of cnt[0..kBinV): kPer consecutive counts per thread
+  constexpr int kPer = kBinV / kBT;
   const uint32_t i0 = threadIdx.x * kPer;
   uint32_t s = 0, mx = 0;
   for (int i = 0; i < kPer; ++i) {
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(kBlock)
     mx = d > mx ? d : mx;
   }
   uint32_t tot;
-  uint32_t run = block_exclusive_scan(s, &tot, lds);
+  uint32_t run = block_exclusive_scan<kBT>(s, &tot, lds);
   for (int i = 0; i < kPer; ++i) {
     const uint32_t v = i0 + i;
     const uint32_t d = cnt[pad(v)];
@@ -231,13 +232,13 @@ __global__ void __launch_bounds__(kBlock)
     cnt[pad(v)] = run;  // becomes the cursor
     run += d;
   }
-  const uint32_t bmax = block_max(mx, lds);
+  const uint32_t bmax = block_max<kBT>(mx, lds);
   if (threadIdx.x == 0) {
     pmax[b] = bmax;
     if (b == nb - 1) offsets[n] = end;
   }
   __syncthreads();
-  for (uint32_t p = base + threadIdx.x; p < end; p += kBlock) {
+  for (uint32_t p = base + threadIdx.x; p < end; p += kBT) {
     const uint64_t pr = pairs[p];
     const uint32_t pos = atomicAdd(&cnt[pad(static_cast<uint32_t>(pr) - v0)], 1u);
     inc[base + pos] = static_cast<uint32_t>(pr >> 32);
@@ -320,10 +321,10 @@ peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t
   uint32_t *pmax = c.take<uint32_t>(z.nb + 1);
   uint32_t *total = pmax + z.nb;
   if (z.ntiles) {
-    hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kBlock), 0, s, edges, m, n,
+    hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
                        (uint32_t)z.nb, z.ntiles, hist, info);
     scan_u32(hist, z.hist, hist, nullptr, part, nullptr, total, nullptr, s);
-    hipLaunchKernelGGL(k_bin_scatter<R>, dim3(z.ntiles), dim3(kBlock), 0, s, edges, m, n,
+    hipLaunchKernelGGL(k_bin_scatter<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
                        (uint32_t)z.nb, z.ntiles, hist, pairs);
   } else {
     // no edges: every bucket is empty
@@ -331,7 +332,7 @@ peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t
                        hist, z.nb, 0u);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(kBlock), 0, s, total, (uint64_t)1, 0u);
   }
-  hipLaunchKernelGGL(k_bin_build, dim3(z.nb), dim3(kBlock), 0, s, pairs, n, (uint32_t)z.nb,
+  hipLaunchKernelGGL(k_bin_build, dim3(z.nb), dim3(kBT), 0, s, pairs, n, (uint32_t)z.nb,
                      z.ntiles ? z.ntiles : 1, hist, total, offsets, inc, deg, pmax);
   hipLaunchKernelGGL(k_max_u32, dim3(1), dim3(kBlock), 0, s, pmax, z.nb, info + 1);
   PEEL_HIP_TRY(hipGetLastError());

@@ -43,7 +43,7 @@ struct Hash {
   uint32_t r;
 };
 
-Hash make_hash(const iblt_desc &d) {
+__host__ __device__ inline Hash make_hash(const iblt_desc &d) {
   Hash h{};
   uint64_t acc = 0;
   h.r = d.r;
@@ -90,15 +90,91 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
+// Plain 32-byte store of an empty cell (the cell a key was listed from holds
+// that key alone, so no other key touches it in the same round).
+__device__ inline void clear_cell(iblt_cell *cell) {
+  uint4 *p = reinterpret_cast<uint4 *>(cell);
+  p[0] = make_uint4(0u, 0u, 0u, 0u);
+  p[1] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__device__ inline void load_cell(const iblt_cell *cell, int32_t *cnt, uint64_t *ks, uint64_t *hs) {
+  const uint4 *p = reinterpret_cast<const uint4 *>(cell);
+  const uint4 a = p[0];
+  const uint4 b = p[1];
+  *cnt = static_cast<int32_t>(a.x);
+  *ks = (uint64_t)a.z | ((uint64_t)a.w << 32);
+  *hs = (uint64_t)b.x | ((uint64_t)b.y << 32);
+}
+
+// True when cell c (already read as cnt/ks/hs) is pure and it is the owner of
+// its key: no cell of the key in a lower subtable is a pure cell of that key.
+// Sets *bad for a count-1 cell whose checksum does not match.
+template <int R>
+__device__ inline bool owns(const Hash &h, const iblt_cell *cells, uint32_t c, int32_t cnt,
+                            uint64_t ks, uint64_t hs, uint32_t *bad) {
+  if (cnt != 1) return false;
+  const uint64_t hx = check_of(h, ks);
+  if (hs != hx) {
+    *bad = 1;
+    return false;
+  }
+  const uint32_t j = subtable_of(h, c);
+#pragma unroll
+  for (int i = 0; i < R - 1; ++i) {
+    if (i >= (int)j) break;
+    int32_t oc;
+    uint64_t ok, oh;
+    load_cell(cells + cell_of(h, i, ks), &oc, &ok, &oh);
+    if (oc == 1 && ok == ks && oh == hx) return false;
+  }
+  return true;
+}
+
+// Deletes key x from its R cells; the cell it was listed from (c_own) is simply
+// cleared.  Calls push(c) for every cell whose count goes 2 -> 1.
+template <int R, typename Push>
+__device__ inline void delete_key(const Hash &h, iblt_cell *cells, uint64_t x, uint32_t c_own,
+                                  Push push) {
+  const uint64_t hx = check_of(h, x);
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const uint32_t c = cell_of(h, j, x);
+    iblt_cell *cell = cells + c;
+    if (c == c_own) {
+      clear_cell(cell);
+      continue;
+    }
+    const int32_t old = atomicSub(&cell->count, 1);
+    atomicXor(reinterpret_cast<unsigned long long *>(&cell->key_sum), (unsigned long long)x);
+    atomicXor(reinterpret_cast<unsigned long long *>(&cell->hash_sum), (unsigned long long)hx);
+    if (old == 2) push(c);
+  }
+}
+
+// ===========================================================================
+// Multi-workgroup listing of one table (persistent kernel, run-time team).
+//
+// Each workgroup keeps the keys it found in this round's detect phase in its
+// own staging slice (with a shared overflow region), applies exactly those
+// keys, and keeps the cells it pushed as its own candidates for the next
+// detect phase.  The hierarchical barrier after detect sums the staged counts
+// and gives each workgroup its exclusive prefix, which places its keys in
+// out_keys without any contended atomic.
+
+constexpr int kLT = 1024;  // threads per listing workgroup
+
 struct ListCtrl {
-  GridSync sync;
+  SumBar bar;
   Team team;
-  uint32_t own[3];   // keys owned in the detect phase feeding round t: own[t % 3]
-  uint32_t cand[2];  // candidates pushed in round t: cand[t % 2]
   uint32_t flags;
   uint32_t rounds;
+  uint32_t team_size;
+  uint32_t pad;
   uint64_t listed;
   unsigned long long count_sum;  // sum of all counts at the start (two's complement)
+  uint32_t ovf_own[2];           // overflow keys found by detect for round u: [u & 1]
+  uint32_t ovf_cand[2];          // overflow candidates pushed by apply of round u: [u & 1]
   uint64_t stamp[256];           // wall clock at each barrier generation (diagnostic)
 };
 
@@ -108,180 +184,169 @@ struct ListArgs {
   uint64_t *out;
   uint64_t out_cap;
   uint64_t *stats;
-  uint32_t *ca;  // candidate lists
-  uint32_t *cb;
+  uint64_t *skeys;   // G * cb staged keys
+  uint32_t *scells;  // G * cb cells they were found in
+  uint32_t *cand;    // G * cb candidate cells
+  uint64_t *okeys;   // ncells overflow keys
+  uint32_t *ocells;  // ncells
+  uint32_t *ocand;   // 2 * ncells overflow candidates
   ListCtrl *ctrl;
   uint64_t limit;
   uint64_t quiet;
   uint32_t ncells;
   uint32_t max_rounds;
+  uint32_t cb;
+  uint32_t grid;
 };
 
 __global__ void k_list_init(ListCtrl *ctrl) {
-  if (threadIdx.x == 0) {
-    ctrl->sync.count = ctrl->sync.gen = ctrl->sync.abort = ctrl->sync.pad = 0;
-    ctrl->team.join = ctrl->team.size = 0;
-    ctrl->own[0] = ctrl->own[1] = ctrl->own[2] = 0;
-    ctrl->cand[0] = ctrl->cand[1] = 0;
-    ctrl->flags = 0;
-    ctrl->rounds = 0;
-    ctrl->listed = 0;
-    ctrl->count_sum = 0;
-  }
-}
-
-// True when cell c (already read as cnt/ks/hs) is pure and it is the owner of
-// its key: no cell of the key in a lower subtable is a pure cell of that key.
-template <int R>
-__device__ inline bool owns(const ListArgs &a, uint32_t c, int32_t cnt, uint64_t ks, uint64_t hs,
-                            uint32_t *flags_bad) {
-  if (cnt != 1) return false;
-  const uint64_t hx = check_of(a.h, ks);
-  if (hs != hx) {
-    *flags_bad = 1;
-    return false;
-  }
-  const uint32_t j = subtable_of(a.h, c);
-#pragma unroll
-  for (int i = 0; i < R - 1; ++i) {
-    if (i >= (int)j) break;
-    const iblt_cell *o = a.cells + cell_of(a.h, i, ks);
-    if (o->count == 1 && o->key_sum == ks && o->hash_sum == hx) return false;
-  }
-  return true;
-}
-
-// Appends `x` (when take) to out[listed_base + ...] with one global atomic per workgroup.
-__device__ inline void append_owned(const ListArgs &a, uint32_t *own_ctr, uint64_t listed_base,
-                                    bool take, uint64_t x, uint32_t *lds, uint32_t *s_base) {
-  uint32_t tot;
-  const uint32_t off = block_exclusive_scan(take ? 1u : 0u, &tot, lds);
-  if (threadIdx.x == 0) *s_base = tot ? atomicAdd(own_ctr, tot) : 0u;
-  __syncthreads();
-  if (take) {
-    const uint64_t pos = listed_base + *s_base + off;
-    if (pos < a.out_cap)
-      a.out[pos] = x;
-    else
-      atomicOr(&a.ctrl->flags, PEEL_FLAG_ENOSPC);
-  }
-  __syncthreads();
+  uint32_t *w = reinterpret_cast<uint32_t *>(ctrl);
+  for (uint32_t i = threadIdx.x; i < sizeof(ListCtrl) / 4; i += blockDim.x) w[i] = 0;
 }
 
 template <int R>
-__global__ void __launch_bounds__(kBlock) k_list_persistent(ListArgs a) {
-  __shared__ uint32_t q[kQueue];
-  __shared__ uint32_t qn;
-  __shared__ uint32_t s_base;
-  __shared__ uint32_t lds[kBlock / kWave + 1];
+__global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
+  __shared__ uint32_t s_own, s_cand, s_bad;
   __shared__ unsigned long long s_sum;
 
   ListCtrl *ctrl = a.ctrl;
-  uint32_t slot, nblocks;
-  if (!team_join(&ctrl->team, a.quiet, a.limit, &slot, &nblocks)) return;
-  const uint64_t gtid = (uint64_t)slot * kBlock + threadIdx.x;
-  const uint64_t gsize = (uint64_t)nblocks * kBlock;
-  uint32_t bad = 0;
+  uint32_t slot, T;
+  if (!team_join(&ctrl->team, a.quiet, a.limit, &slot, &T)) return;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t gtid = (uint64_t)slot * kLT + tid;
+  const uint64_t gsize = (uint64_t)T * kLT;
+  const uint32_t cb = a.cb;
+  const uint32_t N = a.ncells;
+  uint64_t *myKeys = a.skeys + (uint64_t)slot * cb;
+  uint32_t *myOwn = a.scells + (uint64_t)slot * cb;
+  uint32_t *myCand = a.cand + (uint64_t)slot * cb;
 
-  // ---- round-1 detect over every cell -------------------------------------
-  for (uint64_t i = gtid; i < a.max_rounds; i += gsize) a.stats[i] = 0;
-  if (threadIdx.x == 0) s_sum = 0;
-  __syncthreads();
-  long long local_sum = 0;
-  for (uint64_t t0 = (uint64_t)slot * kDenseTile; t0 < a.ncells;
-       t0 += (uint64_t)nblocks * kDenseTile) {
-#pragma unroll
-    for (int it = 0; it < kDenseItems; ++it) {
-      const uint64_t c = t0 + (uint64_t)it * kBlock + threadIdx.x;
-      bool take = false;
-      uint64_t x = 0;
-      if (c < a.ncells) {
-        const iblt_cell cell = a.cells[c];
-        local_sum += cell.count;
-        take = owns<R>(a, static_cast<uint32_t>(c), cell.count, cell.key_sum, cell.hash_sum, &bad);
-        x = cell.key_sum;
-      }
-      append_owned(a, &ctrl->own[1], 0, take, x, lds, &s_base);
+  auto stage = [&](uint64_t x, uint32_t c, uint32_t parity) {
+    const uint32_t pos = atomicAdd(&s_own, 1u);
+    if (pos < cb) {
+      myKeys[pos] = x;
+      myOwn[pos] = c;
+    } else {
+      const uint32_t j = atomicAdd(&ctrl->ovf_own[parity], 1u);
+      a.okeys[j] = x;
+      a.ocells[j] = c;
     }
-  }
-  atomicAdd(&s_sum, (unsigned long long)local_sum);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_sum) atomicAdd(&ctrl->count_sum, s_sum);
-  if (bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
-  bad = 0;
-  if (!grid_barrier(&ctrl->sync, nblocks, a.limit, ctrl->stamp)) return;
+  };
 
-  // ---- rounds ---------------------------------------------------------------
+  // ---- round-1 detect over my range of cells ------------------------------
+  if (tid == 0) {
+    s_own = 0;
+    s_bad = 0;
+    s_sum = 0;
+  }
+  if (slot == 0)
+    for (uint32_t i = tid; i < a.max_rounds; i += kLT) a.stats[i] = 0;
+  __syncthreads();
+  {
+    const uint32_t cr = (N + T - 1) / T;
+    const uint32_t c0 = slot * cr < N ? slot * cr : N;
+    const uint32_t c1 = c0 + cr < N ? c0 + cr : N;
+    long long local = 0;
+    uint32_t bad = 0;
+    for (uint32_t c = c0 + tid; c < c1; c += kLT) {
+      int32_t cnt;
+      uint64_t ks, hs;
+      load_cell(a.cells + c, &cnt, &ks, &hs);
+      local += cnt;
+      if (owns<R>(a.h, a.cells, c, cnt, ks, hs, &bad)) stage(ks, c, 1u);
+    }
+    if (bad) s_bad = 1;
+    atomicAdd(&s_sum, (unsigned long long)local);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (s_sum) atomicAdd(&ctrl->count_sum, s_sum);
+    if (s_bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
+  }
+  uint32_t staged = s_own < cb ? s_own : cb;
+  uint32_t epoch = 0;
+  uint64_t total, prefix;
+  if (!sum_barrier(&ctrl->bar, T, slot, staged, &epoch, a.limit, &total, ctrl->stamp, &prefix))
+    return;
+  uint32_t ovf = __hip_atomic_load(&ctrl->ovf_own[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
   uint64_t listed = 0;
   uint32_t t = 1;
   for (;; ++t) {
-    const uint32_t K = atomic_load_u32(&ctrl->own[t % 3]);
-    const uint32_t flags = atomic_load_u32(&ctrl->flags);
+    const uint64_t K = total + ovf;
     if (K == 0) break;
     if (t > a.max_rounds) {
-      if (gtid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_EROUNDS);
+      if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_EROUNDS);
       break;
     }
-    if (flags & PEEL_FLAG_ENOSPC) break;
-    uint32_t *cand = (t & 1u) ? a.ca : a.cb;
-    uint32_t *cctr = &ctrl->cand[t % 2];
-    if (gtid == 0) {
+    if (listed + K > a.out_cap) {
+      if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_ENOSPC);
+      break;
+    }
+    // outputs of round t, grouped after the previous rounds
+    for (uint32_t i = tid; i < staged; i += kLT) a.out[listed + prefix + i] = myKeys[i];
+    for (uint64_t j = gtid; j < ovf; j += gsize) a.out[listed + total + j] = a.okeys[j];
+    if (slot == 0 && tid == 0) {
       a.stats[t - 1] = K;
-      ctrl->own[(t + 2) % 3] = 0;
-      ctrl->cand[(t + 1) % 2] = 0;
+      ctrl->ovf_cand[(t + 1) & 1] = 0;  // consumed by the detect phase of round t
     }
-    if (threadIdx.x == 0) qn = 0;
+    // apply: delete this round's keys; cells going 2 -> 1 are next round's candidates
+    if (tid == 0) s_cand = 0;
     __syncthreads();
-
-    // apply: delete every key listed this round from its r cells
-    for (uint64_t i = gtid; i < K; i += gsize) {
-      const uint64_t x = a.out[listed + i];
-      const uint64_t hx = check_of(a.h, x);
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        const uint32_t c = cell_of(a.h, j, x);
-        iblt_cell *cell = a.cells + c;
-        const int32_t old = atomicSub(&cell->count, 1);
-        atomicXor(reinterpret_cast<unsigned long long *>(&cell->key_sum), (unsigned long long)x);
-        atomicXor(reinterpret_cast<unsigned long long *>(&cell->hash_sum), (unsigned long long)hx);
-        if (old == 2) {
-          const uint32_t slot = atomicAdd(&qn, 1u);
-          if (slot < kQueue)
-            q[slot] = c;
-          else
-            cand[atomicAdd(cctr, 1u)] = c;
-        }
-      }
-    }
+    const uint32_t par = t & 1;
+    auto push = [&](uint32_t c) {
+      const uint32_t pos = atomicAdd(&s_cand, 1u);
+      if (pos < cb)
+        myCand[pos] = c;
+      else
+        a.ocand[(uint64_t)par * N + atomicAdd(&ctrl->ovf_cand[par], 1u)] = c;
+    };
+    for (uint32_t i = tid; i < staged; i += kLT) delete_key<R>(a.h, a.cells, myKeys[i], myOwn[i], push);
+    for (uint64_t j = gtid; j < ovf; j += gsize) delete_key<R>(a.h, a.cells, a.okeys[j], a.ocells[j], push);
     __syncthreads();
-    const uint32_t nq = qn < kQueue ? qn : kQueue;
-    if (threadIdx.x == 0) s_base = nq ? atomicAdd(cctr, nq) : 0u;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nq; i += kBlock) cand[s_base + i] = q[i];
-    if (!grid_barrier(&ctrl->sync, nblocks, a.limit, ctrl->stamp)) return;
-
-    // detect for round t+1 over this round's candidates
+    const uint32_t ncand = s_cand < cb ? s_cand : cb;
+    uint64_t dummy;
+    if (!sum_barrier(&ctrl->bar, T, slot, 0, &epoch, a.limit, &dummy, ctrl->stamp)) return;
     listed += K;
-    const uint32_t nc = atomic_load_u32(cctr);
-    const uint64_t span = (nc + gsize - 1) / gsize * gsize;  // uniform trip count
-    for (uint64_t i = gtid; i < span; i += gsize) {
-      bool take = false;
-      uint64_t x = 0;
-      if (i < nc) {
-        const uint32_t c = cand[i];
-        const iblt_cell cell = a.cells[c];
-        take = owns<R>(a, c, cell.count, cell.key_sum, cell.hash_sum, &bad);
-        x = cell.key_sum;
-      }
-      append_owned(a, &ctrl->own[(t + 1) % 3], listed, take, x, lds, &s_base);
+    // detect for round t+1 over my candidates and a share of the overflow
+    const uint32_t npar = (t + 1) & 1;
+    if (tid == 0) {
+      s_own = 0;
+      s_bad = 0;
+      if (slot == 0) ctrl->ovf_own[par] = 0;  // consumed by round t
     }
-    if (bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
-    bad = 0;
-    if (!grid_barrier(&ctrl->sync, nblocks, a.limit, ctrl->stamp)) return;
+    __syncthreads();
+    {
+      uint32_t bad = 0;
+      for (uint32_t i = tid; i < ncand; i += kLT) {
+        const uint32_t c = myCand[i];
+        int32_t cnt;
+        uint64_t ks, hs;
+        load_cell(a.cells + c, &cnt, &ks, &hs);
+        if (owns<R>(a.h, a.cells, c, cnt, ks, hs, &bad)) stage(ks, c, npar);
+      }
+      const uint32_t ovc =
+          __hip_atomic_load(&ctrl->ovf_cand[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (uint64_t j = gtid; j < ovc; j += gsize) {
+        const uint32_t c = a.ocand[(uint64_t)par * N + j];
+        int32_t cnt;
+        uint64_t ks, hs;
+        load_cell(a.cells + c, &cnt, &ks, &hs);
+        if (owns<R>(a.h, a.cells, c, cnt, ks, hs, &bad)) stage(ks, c, npar);
+      }
+      if (bad) s_bad = 1;
+    }
+    __syncthreads();
+    if (tid == 0 && s_bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
+    staged = s_own < cb ? s_own : cb;
+    if (!sum_barrier(&ctrl->bar, T, slot, staged, &epoch, a.limit, &total, ctrl->stamp, &prefix))
+      return;
+    ovf = __hip_atomic_load(&ctrl->ovf_own[npar], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (gtid == 0) {
+  if (slot == 0 && tid == 0) {
     ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
     ctrl->listed = listed;
+    ctrl->team_size = T;
   }
 }
 
@@ -291,17 +356,167 @@ __global__ void k_list_finish(const ListCtrl *ctrl, uint32_t r, uint64_t *summar
   const long long total = (long long)ctrl->count_sum;
   const long long keys = total / (long long)r;
   uint32_t flags = ctrl->flags;
-  if (ctrl->sync.abort) flags |= PEEL_FLAG_TIMEOUT;
+  if (ctrl->bar.abort) flags |= PEEL_FLAG_TIMEOUT;
   summary[0] = ctrl->listed;
   summary[1] = ctrl->rounds;
   summary[2] = (uint64_t)(keys - (long long)ctrl->listed);
   summary[3] = flags;
-  summary[4] = ctrl->team.size;
+  summary[4] = ctrl->team_size;
   summary[5] = summary[6] = summary[7] = 0;
 }
 
-size_t list_ws_bytes(uint64_t ncells) {
-  return align_up(sizeof(ListCtrl)) + 2 * align_up((size_t)ncells * 4);
+// ===========================================================================
+// Batched listing: many independent tables in one launch, one workgroup per
+// table at a time (tables taken in the given order from a shared ticket), the
+// round barrier being the workgroup barrier.
+
+// Lists one table with one NT-thread workgroup.  cand and own are scratch of
+// ncells entries each.  Writes the table's outputs like iblt_list.
+template <int R, int NT>
+__device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, uint64_t *out,
+                                 uint64_t out_cap, uint64_t *stats, uint32_t max_rounds,
+                                 uint64_t *summary, uint32_t *cand, uint32_t *own) {
+  __shared__ uint32_t s_k, s_c, s_bad, s_flags;
+  __shared__ unsigned long long s_sum;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < max_rounds; i += NT) stats[i] = 0;
+  if (tid == 0) {
+    s_k = 0;
+    s_bad = 0;
+    s_flags = 0;
+    s_sum = 0;
+  }
+  __syncthreads();
+  uint64_t listed = 0;
+  // round-1 detect over every cell: owned keys go straight to out[listed + pos]
+  {
+    long long local = 0;
+    uint32_t bad = 0;
+    for (uint32_t c = tid; c < N; c += NT) {
+      int32_t cnt;
+      uint64_t ks, hs;
+      load_cell(cells + c, &cnt, &ks, &hs);
+      local += cnt;
+      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) {
+        const uint32_t pos = atomicAdd(&s_k, 1u);
+        if (pos < N) own[pos] = c;
+        if (listed + pos < out_cap) out[listed + pos] = ks;
+      }
+    }
+    if (bad) s_bad = 1;
+    atomicAdd(&s_sum, (unsigned long long)local);
+  }
+  __syncthreads();
+  uint32_t t = 1;
+  for (;; ++t) {
+    const uint32_t K = s_k;
+    if (K == 0) break;
+    if (t > max_rounds) {
+      if (tid == 0) s_flags |= PEEL_FLAG_EROUNDS;
+      break;
+    }
+    if (listed + K > out_cap) {
+      if (tid == 0) s_flags |= PEEL_FLAG_ENOSPC;
+      break;
+    }
+    if (tid == 0) {
+      stats[t - 1] = K;
+      s_c = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < K; i += NT)
+      delete_key<R>(h, cells, out[listed + i], own[i], [&](uint32_t c) { cand[atomicAdd(&s_c, 1u)] = c; });
+    __syncthreads();
+    listed += K;
+    const uint32_t nc = s_c;
+    if (tid == 0) s_k = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (uint32_t i = tid; i < nc; i += NT) {
+      const uint32_t c = cand[i];
+      int32_t cnt;
+      uint64_t ks, hs;
+      load_cell(cells + c, &cnt, &ks, &hs);
+      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) {
+        const uint32_t pos = atomicAdd(&s_k, 1u);
+        own[pos] = c;
+        if (listed + pos < out_cap) out[listed + pos] = ks;
+      }
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const long long keys = (long long)s_sum / (long long)R;
+    summary[0] = listed;
+    summary[1] = t - 1 < max_rounds ? t - 1 : max_rounds;
+    summary[2] = (uint64_t)(keys - (long long)listed);
+    summary[3] = s_flags | (s_bad ? PEEL_FLAG_ECORRUPT : 0u);
+    summary[4] = 1;
+    summary[5] = summary[6] = summary[7] = 0;
+  }
+  __syncthreads();
+}
+
+struct BatchCtrl {
+  uint32_t ticket;
+  uint32_t pad[63];
+};
+
+template <int NT>
+__global__ void __launch_bounds__(NT)
+    k_list_batched(const iblt_batch_entry *entries, uint32_t ntables, uint32_t max_rounds,
+                   BatchCtrl *ctrl, uint32_t *scratch, uint64_t max_cells) {
+  __shared__ uint32_t s_t;
+  uint32_t *cand = scratch + (uint64_t)blockIdx.x * 2 * max_cells;
+  uint32_t *own = cand + max_cells;
+  for (;;) {
+    if (threadIdx.x == 0) s_t = atomicAdd(&ctrl->ticket, 1u);
+    __syncthreads();
+    const uint32_t ti = s_t;
+    __syncthreads();
+    if (ti >= ntables) return;
+    const iblt_batch_entry e = entries[ti];
+    const Hash h = make_hash(e.desc);
+    const uint32_t N = static_cast<uint32_t>(e.desc.ncells);
+    switch (e.desc.r) {
+      case 2: list_table_block<2, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
+      case 3: list_table_block<3, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
+      case 4: list_table_block<4, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
+      case 5: list_table_block<5, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
+      case 6: list_table_block<6, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
+      case 7: list_table_block<7, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
+      default: list_table_block<8, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
+    }
+  }
+}
+
+__global__ void k_batch_init(BatchCtrl *ctrl) {
+  if (threadIdx.x == 0) ctrl->ticket = 0;
+}
+
+// ===========================================================================
+// Host side.
+
+struct ListLayout {
+  size_t ctrl, skeys, scells, cand, okeys, ocells, ocand, total;
+  uint32_t grid, cb;
+};
+
+ListLayout list_layout(uint64_t ncells) {
+  ListLayout L{};
+  L.grid = static_cast<uint32_t>(device_info().cus);  // one 1024-thread workgroup per CU
+  L.cb = static_cast<uint32_t>((ncells + L.grid - 1) / L.grid + 4096);
+  const uint64_t slots = (uint64_t)L.grid * L.cb;
+  L.ctrl = align_up(sizeof(ListCtrl));
+  L.skeys = align_up(slots * 8);
+  L.scells = align_up(slots * 4);
+  L.cand = align_up(slots * 4);
+  L.okeys = align_up(ncells * 8);
+  L.ocells = align_up(ncells * 4);
+  L.ocand = align_up(2 * ncells * 4);
+  L.total = L.ctrl + L.skeys + L.scells + L.cand + L.okeys + L.ocells + L.ocand;
+  return L;
 }
 
 bool desc_ok(const iblt_desc *d) {
@@ -319,16 +534,20 @@ peel_status launch_insert(const Hash &h, iblt_cell *cells, const uint64_t *keys,
 
 template <int R>
 peel_status launch_list(ListArgs &a, hipStream_t s) {
-  const void *fn = reinterpret_cast<const void *>(&k_list_persistent<R>);
-  const int cap = coresident_blocks(fn, kBlock, 0);
-  uint64_t want = ((uint64_t)a.ncells + kDenseTile - 1) / kDenseTile;
-  if (want < 1) want = 1;
-  const unsigned grid = static_cast<unsigned>(want < (uint64_t)cap ? want : (uint64_t)cap);
-  if (device_info().debug) std::fprintf(stderr, "[peel] persistent grid %u (cap %d)\n", grid, cap);
-  // A plain launch: the kernel forms its team of resident workgroups itself.
-  hipLaunchKernelGGL(k_list_persistent<R>, dim3(grid), dim3(kBlock), 0, s, a);
+  if (device_info().debug) std::fprintf(stderr, "[peel] list grid %u\n", a.grid);
+  hipLaunchKernelGGL(k_list_persistent<R>, dim3(a.grid), dim3(kLT), 0, s, a);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
+}
+
+size_t batched_ws_bytes(uint32_t ntables, uint64_t max_cells, uint32_t grid) {
+  (void)ntables;
+  return align_up(sizeof(BatchCtrl)) + align_up((uint64_t)grid * 2 * max_cells * 4);
+}
+
+uint32_t batched_grid(uint32_t ntables) {
+  const uint32_t g = static_cast<uint32_t>(2 * device_info().cus);
+  return ntables < g ? (ntables ? ntables : 1) : g;
 }
 
 }  // namespace
@@ -339,6 +558,7 @@ using namespace peel;
 extern "C" peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
                                    uint64_t nkeys, void *stream) {
   if (!desc_ok(desc) || !cells || (nkeys && !keys)) return PEEL_EINVAL;
+  if (reinterpret_cast<uintptr_t>(cells) % 32) return PEEL_EINVAL;
   if (nkeys == 0) return PEEL_OK;
   const Hash h = make_hash(*desc);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -354,7 +574,7 @@ extern "C" peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, cons
 }
 
 extern "C" size_t iblt_list_workspace(const iblt_desc *desc) {
-  return desc_ok(desc) ? list_ws_bytes(desc->ncells) : 0;
+  return desc_ok(desc) ? list_layout(desc->ncells).total : 0;
 }
 
 extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
@@ -363,14 +583,26 @@ extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64
   if (!desc_ok(desc) || !cells || (out_cap && !out_keys) || !round_stats || !summary || !ws ||
       max_rounds == 0)
     return PEEL_EINVAL;
-  if (ws_bytes < list_ws_bytes(desc->ncells)) return PEEL_ENOSPC;
+  if (reinterpret_cast<uintptr_t>(cells) % 32) return PEEL_EINVAL;
+  const ListLayout L = list_layout(desc->ncells);
+  if (ws_bytes < L.total) return PEEL_ENOSPC;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Carver c(ws);
+  char *base = static_cast<char *>(ws);
   ListArgs a;
   a.h = make_hash(*desc);
-  a.ctrl = c.take<ListCtrl>(1);
-  a.ca = c.take<uint32_t>(desc->ncells);
-  a.cb = c.take<uint32_t>(desc->ncells);
+  a.ctrl = reinterpret_cast<ListCtrl *>(base);
+  base += L.ctrl;
+  a.skeys = reinterpret_cast<uint64_t *>(base);
+  base += L.skeys;
+  a.scells = reinterpret_cast<uint32_t *>(base);
+  base += L.scells;
+  a.cand = reinterpret_cast<uint32_t *>(base);
+  base += L.cand;
+  a.okeys = reinterpret_cast<uint64_t *>(base);
+  base += L.okeys;
+  a.ocells = reinterpret_cast<uint32_t *>(base);
+  base += L.ocells;
+  a.ocand = reinterpret_cast<uint32_t *>(base);
   a.cells = cells;
   a.out = out_keys;
   a.out_cap = out_cap;
@@ -379,7 +611,9 @@ extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64
   a.quiet = device_info().team_quiet_ticks;
   a.ncells = static_cast<uint32_t>(desc->ncells);
   a.max_rounds = max_rounds;
-  hipLaunchKernelGGL(k_list_init, dim3(1), dim3(64), 0, s, a.ctrl);
+  a.cb = L.cb;
+  a.grid = L.grid;
+  hipLaunchKernelGGL(k_list_init, dim3(1), dim3(256), 0, s, a.ctrl);
   PEEL_HIP_TRY(hipGetLastError());
   peel_status st;
   switch (desc->r) {
@@ -393,6 +627,40 @@ extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64
   }
   if (st) return st;
   hipLaunchKernelGGL(k_list_finish, dim3(1), dim3(64), 0, s, a.ctrl, desc->r, summary);
+  PEEL_HIP_TRY(hipGetLastError());
+  return PEEL_OK;
+}
+
+extern "C" size_t iblt_list_batched_workspace(uint32_t ntables, uint64_t max_cells) {
+  return batched_ws_bytes(ntables, max_cells, batched_grid(ntables));
+}
+
+extern "C" peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32_t ntables,
+                                         uint64_t max_cells, uint32_t max_rounds,
+                                         uint32_t block_threads, void *ws, size_t ws_bytes,
+                                         void *stream) {
+  if ((ntables && !entries) || max_rounds == 0 || max_cells >= (1ull << 32) || !ws)
+    return PEEL_EINVAL;
+  if (block_threads == 0) block_threads = 512;
+  if (block_threads != 256 && block_threads != 512 && block_threads != 1024) return PEEL_EINVAL;
+  const uint32_t grid = batched_grid(ntables);
+  if (ws_bytes < batched_ws_bytes(ntables, max_cells, grid)) return PEEL_ENOSPC;
+  if (ntables == 0) return PEEL_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BatchCtrl *ctrl = static_cast<BatchCtrl *>(ws);
+  uint32_t *scratch = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + align_up(sizeof(BatchCtrl)));
+  hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(64), 0, s, ctrl);
+  switch (block_threads) {
+    case 256:
+      hipLaunchKernelGGL(k_list_batched<256>, dim3(grid), dim3(256), 0, s, entries, ntables, max_rounds, ctrl, scratch, max_cells);
+      break;
+    case 512:
+      hipLaunchKernelGGL(k_list_batched<512>, dim3(grid), dim3(512), 0, s, entries, ntables, max_rounds, ctrl, scratch, max_cells);
+      break;
+    default:
+      hipLaunchKernelGGL(k_list_batched<1024>, dim3(grid), dim3(1024), 0, s, entries, ntables, max_rounds, ctrl, scratch, max_cells);
+      break;
+  }
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }

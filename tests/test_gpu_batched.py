@@ -1,0 +1,194 @@
+"""GPU parity of the batched IBLT listing (many tables, one launch).
+
+Every table of a batch must come out exactly as the oracle lists it, round by
+round, and exactly as iblt_list lists it alone.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1302_7014_amd as pk
+from oracle import native, theory
+from workloads import configs, gen
+
+from gpu_helpers import dev_u64, host_u64, need_gpu, say, table_to_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+def _make_tables(specs, max_rounds):
+    """specs: [(ncells, r, nkeys, seed)] -> (BatchTables, keys, pristine copies)."""
+    tables, keys, pristine = [], [], []
+    for ncells, r, nkeys, seed in specs:
+        k = gen.distinct_keys(nkeys, seed)
+        d = pk.iblt_desc(ncells, r, gen.table_seed(seed))
+        cells = pk.iblt_table(ncells, "cuda")
+        if nkeys:
+            pk.iblt_insert(d, cells, dev_u64(k))
+        tables.append(pk.batch_table(d, cells, max_rounds))
+        keys.append(k)
+        pristine.append(cells.clone())
+    torch.cuda.synchronize()
+    return tables, keys, pristine
+
+
+def _result(t: pk.BatchTable):
+    s = t.summary.cpu().numpy()
+    listed, rounds = int(s[0]), int(s[1])
+    K = host_u64(t.round_stats)[:rounds]
+    ks = host_u64(t.keys)[:listed]
+    groups, off = [], 0
+    for kk in K.tolist():
+        groups.append(np.sort(ks[off: off + kk]))
+        off += kk
+    return s, K, groups
+
+
+def _check_against_oracle(t, k, max_rounds):
+    s, K, groups = _result(t)
+    o_tab = native.iblt_insert(t.desc.ncells, t.desc.r, t.desc.seed, k)
+    o = native.iblt_list_rounds(o_tab, max_rounds=max_rounds, out_cap=t.keys.numel())
+    assert int(s[1]) == o.rounds
+    assert np.array_equal(K, o.K)
+    for a, b in zip(groups, o.per_round()):
+        assert np.array_equal(a, b)
+    count, ksum, hsum, ok = table_to_numpy(t.cells)
+    assert ok
+    assert np.array_equal(count, o_tab.count)
+    assert np.array_equal(ksum, o_tab.key_sum) and np.array_equal(hsum, o_tab.hash_sum)
+    if o.status == native.OK:
+        assert int(s[3]) == 0 and int(s[2]) == k.size - o.keys.size
+
+
+def _specs(n, seed, lo=6, hi=14, rs=(2, 3, 4, 5)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        r = int(rng.choice(rs))
+        N = max(r, int(2 ** rng.uniform(lo, hi)))
+        cs = theory.cstar(2, r)[0] if r > 2 else 0.5
+        load = rng.uniform(0.3, 1.2) * cs
+        out.append((N, r, int(load * N), 1000 * seed + i))
+    return out
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_batched_matches_oracle(threads):
+    need_gpu()
+    specs = _specs(48, 3)
+    specs.sort(key=lambda x: -x[0])
+    tables, keys, _ = _make_tables(specs, 256)
+    ent = pk.batch_entries(tables, "cuda")
+    say("batched", len(tables), "threads", threads)
+    pk.iblt_list_batched(ent, len(tables), max(x[0] for x in specs), 256, block_threads=threads)
+    torch.cuda.synchronize()
+    for t, k in zip(tables, keys):
+        _check_against_oracle(t, k, 256)
+
+
+def test_batched_equals_each_table_alone():
+    need_gpu()
+    specs = _specs(24, 5, lo=8, hi=16)
+    tables, keys, pristine = _make_tables(specs, 128)
+    ent = pk.batch_entries(tables, "cuda")
+    say("batched vs alone")
+    pk.iblt_list_batched(ent, len(tables), max(x[0] for x in specs), 128)
+    torch.cuda.synchronize()
+    for t, p in zip(tables, pristine):
+        alone = pk.iblt_list(t.desc, p, max_rounds=128)
+        torch.cuda.synchronize()
+        sb, Kb, gb = _result(t)
+        sa = alone.summary.cpu().numpy()
+        assert int(sa[0]) == int(sb[0]) and int(sa[1]) == int(sb[1]) and int(sa[3]) == int(sb[3])
+        ka = host_u64(alone.keys)[: int(sa[0])]
+        off = 0
+        for g in gb:
+            assert np.array_equal(np.sort(ka[off: off + g.size]), g)
+            off += g.size
+        assert torch.equal(p, t.cells)
+
+
+def test_batched_limits_and_degenerate():
+    need_gpu()
+    specs = [(3, 3, 0, 1), (3, 3, 1, 2), (5, 4, 3, 3), (4096, 3, 2500, 4), (4096, 3, 3000, 5)]
+    tables, keys, _ = _make_tables(specs, 64)
+    # the last table gets a tiny output capacity and the fourth a tiny round limit
+    tables[-1] = pk.batch_table(tables[-1].desc, tables[-1].cells, 64, out_cap=10)
+    ent = pk.batch_entries(tables, "cuda")
+    say("limits")
+    pk.iblt_list_batched(ent, len(tables), 4096, 64)
+    torch.cuda.synchronize()
+    for t, k in zip(tables[:-1], keys[:-1]):
+        _check_against_oracle(t, k, 64)
+    s, _, _ = _result(tables[-1])
+    assert int(s[3]) & 0x4  # ENOSPC
+    _check_against_oracle(tables[-1], keys[-1], 64)
+
+
+def test_batched_in_a_captured_graph_replays():
+    need_gpu()
+    specs = _specs(32, 7, lo=8, hi=13)
+    tables, keys, pristine = _make_tables(specs, 128)
+    ent = pk.batch_entries(tables, "cuda")
+    maxc = max(x[0] for x in specs)
+    ws = pk.workspace(pk.iblt_list_batched_workspace(len(tables), maxc), "cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm up on the capture stream
+        pk.iblt_list_batched(ent, len(tables), maxc, 128, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    eager = [_result(t) for t in tables]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pk.iblt_list_batched(ent, len(tables), maxc, 128, ws=ws)
+    for rep in range(3):
+        for t, p in zip(tables, pristine):
+            t.cells.copy_(p)
+        torch.cuda.synchronize()
+        say("graph replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        for t, (se, Ke, ge) in zip(tables, eager):
+            sr, Kr, gr = _result(t)
+            assert np.array_equal(se[:4], sr[:4]) and np.array_equal(Ke, Kr)
+            for a, b in zip(ge, gr):
+                assert np.array_equal(a, b)
+
+
+def test_config_batched_sample():
+    # The 4096-table workload (cells log-uniform in [2^10, 2^20], load 0.5-0.8 c*):
+    # all listed in one launch; 24 tables checked against the oracle, and every
+    # table below threshold must come back whole.
+    need_gpu()
+    spec = configs.batched_main()
+    draw = spec.draw(1)
+    rng = np.random.default_rng(0)
+    pick = set(rng.choice(len(draw), 24, replace=False).tolist())
+    specs = [(N, spec.r, m, ks) for (N, m, ks, _) in draw]
+    order = sorted(range(len(specs)), key=lambda i: -specs[i][0])
+    tables, keys = [], []
+    for i in order:
+        N, r, m, ks = specs[i]
+        k = gen.distinct_keys(m, ks)
+        d = pk.iblt_desc(N, r, draw[i][3])
+        cells = pk.iblt_table(N, "cuda")
+        pk.iblt_insert(d, cells, dev_u64(k))
+        tables.append(pk.batch_table(d, cells, 256))
+        keys.append(k if i in pick else m)
+    ent = pk.batch_entries(tables, "cuda")
+    torch.cuda.synchronize()
+    say("config batched 4096")
+    pk.iblt_list_batched(ent, len(tables), max(x[0] for x in specs), 256)
+    torch.cuda.synchronize()
+    complete = 0
+    for t, k in zip(tables, keys):
+        s = t.summary.cpu().numpy()
+        assert int(s[3]) & ~0x0 == 0 or int(s[2]) > 0
+        if isinstance(k, np.ndarray):
+            # this table's inputs were kept: check it against the oracle
+            o_tab = native.iblt_insert(t.desc.ncells, t.desc.r, t.desc.seed, k)
+            o = native.iblt_list_rounds(o_tab, max_rounds=256)
+            assert int(s[0]) == o.keys.size and int(s[1]) == o.rounds
+        complete += int(s[2]) == 0
+    assert complete >= 0.95 * len(tables)
