@@ -197,6 +197,133 @@ def bench_iblt(spec, reps):
     }
 
 
+def bench_batched(spec, reps):
+    """One launch for every table (block-per-table schedule) vs one iblt_list per table."""
+    draw = spec.draw(1)
+    order = sorted(range(len(draw)), key=lambda i: -draw[i][0])
+    dev = torch.device("cuda", 0)
+    tables, pristine, nkeys = [], [], 0
+    for i in order:
+        N, m, kseed, tseed = draw[i]
+        keys = torch.from_numpy(gen.distinct_keys(m, kseed).view(np.int64)).to(dev)
+        d = pk.iblt_desc(N, spec.r, tseed)
+        cells = pk.iblt_table(N, dev)
+        pk.iblt_insert(d, cells, keys)
+        tables.append(pk.batch_table(d, cells, 256))
+        pristine.append(cells.clone())
+        nkeys += m
+    ent = pk.batch_entries(tables, dev)
+    maxc = max(x[0] for x in draw)
+    ws = pk.workspace(pk.iblt_list_batched_workspace(len(tables), maxc), dev)
+    torch.cuda.synchronize()
+
+    def reset():
+        for t, p in zip(tables, pristine):
+            t.cells.copy_(p)
+        torch.cuda.synchronize()
+
+    # capture the batched call in a graph
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pk.iblt_list_batched(ent, len(tables), maxc, 256, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    reset()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        pk.iblt_list_batched(ent, len(tables), maxc, 256, ws=ws)
+    tb = Timer()
+    for _ in range(reps):
+        reset()
+        with tb:
+            graph.replay()
+        tb.collect()
+    listed = sum(int(t.summary[0].item()) for t in tables)
+    incomplete = sum(int(t.summary[2].item()) > 0 for t in tables)
+    # one plain launch per table, same stream, each table listed alone
+    wsl = pk.workspace(max(pk.iblt_list_workspace(t.desc) for t in tables), dev)
+    outs = [pk.ListOut(t.keys, t.round_stats, t.summary) for t in tables]
+    tp = Timer()
+    reset()
+    with tp:
+        for t, o in zip(tables, outs):
+            pk.iblt_list(t.desc, t.cells, max_rounds=256, out=o, ws=wsl)
+    tp.collect()
+    listed_plain = sum(int(t.summary[0].item()) for t in tables)
+    bt = float(np.median(tb.ms))
+    pt = tp.ms[0]
+    return {
+        "workload": spec.name, "tables": len(tables), "cells": int(sum(x[0] for x in draw)),
+        "keys": nkeys, "listed": listed, "incomplete_tables": incomplete,
+        "batched_graph_ms": bt, "plain_per_table_ms": pt, "speedup": pt / bt,
+        "batched_keys_per_s": listed / (bt * 1e-3), "plain_keys_per_s": listed_plain / (pt * 1e-3),
+        "listed_equal": listed == listed_plain,
+    }
+
+
+def bench_serve(spec, n_cal, n_rate, warm):
+    """Served decoding: saturated rate, then p50/p99 at 0.3/0.6/0.9 of it, continuous
+    batching vs the one-at-a-time FIFO server, same requests."""
+    from paper_1302_7014_amd.serve import ContinuousServer, FifoServer, Request, latency_stats
+
+    def fill(q, out):
+        out.copy_(gen.distinct_keys_torch(q.nkeys, q.key_seed, out.device))
+
+    def reqs(count, rate, seed):
+        return [Request(i, *x) for i, x in enumerate(spec.requests(count, rate, seed))]
+
+    def measured(done):
+        return latency_stats([q for q in done if q.rid >= warm])
+
+    cont = ContinuousServer(spec.budget_bytes, fill, max_cells=1 << 22)
+    cal = latency_stats(cont.run(reqs(n_cal, 0.0, 5)))
+    lam = cal["req_per_s"]
+    out = {"workload": spec.name, "budget_gb": spec.budget_bytes / 2 ** 30,
+           "saturated_req_per_s": lam, "warmup_requests": warm, "rates": []}
+    fifo = FifoServer(spec.budget_bytes, fill)
+    for i, frac in enumerate((0.3, 0.6, 0.9)):
+        rate = frac * lam
+        log(f"serving at {rate:.0f} req/s")
+        c = measured(cont.run(reqs(n_rate + warm, rate, 100 + i)))
+        f = measured(fifo.run(reqs(n_rate + warm, rate, 100 + i)))
+        out["rates"].append({"fraction": frac, "rate_req_per_s": rate, "continuous": c, "fifo": f})
+    out["peak_budget_used_gb"] = cont.arena.peak / 2 ** 30
+    out["batches"] = cont.batches
+    return out
+
+
+def copy_probe():
+    """A plain device copy of 1 GiB, for calibrating the HBM byte counters."""
+    dev = torch.device("cuda", 0)
+    a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}))
+
+
+def traffic_from_profile(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    ent = doc.get(kernel)
+    if not ent:
+        return None
+    src = os.path.join(ROOT, ent["source"])
+    if not os.path.exists(src):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if digest != ent["source_sha256"]:
+        return None
+    return ent["bytes_per_launch"]
+
+
 def cpu_baseline(spec, e_host):
     """The oracle's round-synchronous peel on the same workload, single-threaded."""
     from oracle import native  # CPU-baseline leg only
@@ -217,6 +344,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-iblt", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="also time every c of the n=2^24 sweep")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1500, help="measured requests per rate")
+    ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the peel and the IBLT listing run on a single MI355X "
@@ -226,6 +357,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe()
+        return
     pk.lib()
 
     spec = configs.kcore_sweep(0.70)
@@ -234,7 +368,7 @@ def main():
     value = kc["m_removed"] / (kc["wall_s"] / args.steps)
     # dominant kernel: the longer of the two calls
     if kc["peel_ms"] >= kc["build_ms"]:
-        dom, dom_ms, dom_bytes = "k_peel_persistent", kc["peel_ms"], kc["peel_bytes"]
+        dom, dom_ms, dom_bytes = "k_peel_owner", kc["peel_ms"], kc["peel_bytes"]
     else:
         dom, dom_ms, dom_bytes = "hg_build", kc["build_ms"], kc["build_bytes"]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
@@ -247,10 +381,17 @@ def main():
         "rounds": kc["rounds"], "edge_rounds": kc["edge_rounds"],
         "core_vertices": kc["core_vertices"],
     }
+    if not args.no_batched:
+        log("batched IBLT listing (4096 tables)")
+        extra["batched"] = bench_batched(configs.batched_main(), 3)
     if not args.no_iblt:
         log("IBLT 2^24 cells")
         extra["iblt"] = [bench_iblt(configs.iblt_main(), 5),
                          bench_iblt(configs.iblt_paper(3, 0.75), 5)]
+    torch.cuda.empty_cache()
+    if not args.no_serve:
+        log("served decoding")
+        extra["serve"] = bench_serve(configs.served_main(), 600, args.serve_requests, 200)
     if args.sweep:
         sw = []
         for c in configs.SWEEP_C:
@@ -268,7 +409,8 @@ def main():
         "config": {"workload": spec.name, "n": spec.n, "m": spec.m, "r": spec.r, "k": spec.k,
                    "model": spec.model, "seed": 1, "step": "hg_build + peel_kcore"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile(dom)},
         "extra": extra,
     }
     if not args.no_cpu:

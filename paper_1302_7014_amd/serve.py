@@ -1,0 +1,284 @@
+"""Continuous-batching IBLT decode server on one GPU.
+
+Requests are IBLT list jobs of mixed sizes.  The server keeps every admitted
+table resident in a fixed HBM arena (the budget), admits arrivals first come
+first served as arena space frees up, and runs the GPU as a pipeline:
+
+* admission: the request's table and buffers are carved from the arena, its
+  keys are produced on the device by the caller's ``fill_keys`` and inserted
+  with ``iblt_insert`` on the insert stream (this stands for receiving the
+  table), overlapping whatever listing is running;
+* listing: every table inserted and not yet listed is listed in one
+  ``iblt_list_batched`` launch on a list stream; up to ``max_inflight`` such
+  launches run at once, so a request that arrives during a long batch does not
+  wait for it to end;
+* retirement: when a launch's completion event fires, its requests complete,
+  their arena space is freed and their results (the summary) are kept.
+
+``FifoServer`` is the plain baseline: one request at a time, insert then
+``iblt_list`` on one stream.
+
+Latency of a request = (host clock when its completion is observed) - (its
+arrival time on the same clock).  The loop polls events with short sleeps.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import binding as pk
+
+_ALIGN = 256
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float     # seconds after the start of the run
+    r: int
+    ncells: int
+    nkeys: int
+    key_seed: int
+    table_seed: int
+    # filled by the server
+    admitted: float = -1.0
+    done: float = -1.0
+    summary: np.ndarray | None = None
+    keys_out: np.ndarray | None = None
+    _alloc: list = field(default_factory=list, repr=False)
+    _table: object = field(default=None, repr=False)
+    _event: object = field(default=None, repr=False)
+
+    def footprint(self, max_rounds: int) -> int:
+        """Arena bytes: cells (32 B each), output keys (8 B per cell), the inserted
+        keys (8 B each), round stats and summary."""
+        pieces = [32 * self.ncells, 8 * self.ncells, 8 * max(self.nkeys, 1), 8 * max_rounds, 64]
+        return sum(_round(p) for p in pieces)
+
+
+def _round(n: int) -> int:
+    return (n + _ALIGN - 1) // _ALIGN * _ALIGN
+
+
+class Arena:
+    """First-fit allocator over one device buffer of ``budget`` bytes (the HBM budget)."""
+
+    def __init__(self, budget: int, device):
+        self.budget = _round(budget)
+        self.buf = torch.empty(self.budget, dtype=torch.uint8, device=device)
+        self.free_list = [(0, self.budget)]  # (offset, size), sorted by offset
+        self.used = 0
+        self.peak = 0
+
+    def alloc(self, nbytes: int):
+        nbytes = _round(nbytes)
+        for i, (off, size) in enumerate(self.free_list):
+            if size >= nbytes:
+                if size == nbytes:
+                    self.free_list.pop(i)
+                else:
+                    self.free_list[i] = (off + nbytes, size - nbytes)
+                self.used += nbytes
+                self.peak = max(self.peak, self.used)
+                return off, nbytes
+        return None
+
+    def free(self, off: int, nbytes: int) -> None:
+        self.used -= nbytes
+        fl = self.free_list
+        lo, hi = 0, len(fl)
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if fl[mid][0] < off:
+                lo = mid + 1
+            else:
+                hi = mid
+        fl.insert(lo, (off, nbytes))
+        # merge with the neighbours
+        if lo + 1 < len(fl) and fl[lo][0] + fl[lo][1] == fl[lo + 1][0]:
+            fl[lo] = (fl[lo][0], fl[lo][1] + fl[lo + 1][1])
+            fl.pop(lo + 1)
+        if lo > 0 and fl[lo - 1][0] + fl[lo - 1][1] == fl[lo][0]:
+            fl[lo - 1] = (fl[lo - 1][0], fl[lo - 1][1] + fl[lo][1])
+            fl.pop(lo)
+
+    def view(self, off: int, nbytes: int, dtype) -> torch.Tensor:
+        return self.buf[off: off + nbytes].view(dtype)
+
+
+class _Base:
+    def __init__(self, budget: int, fill_keys, max_rounds: int = 256, keep_keys: bool = False,
+                 device="cuda"):
+        self.device = torch.device(device)
+        self.arena = Arena(budget, self.device)
+        self.fill_keys = fill_keys
+        self.max_rounds = max_rounds
+        self.keep_keys = keep_keys
+        self.rejected = []
+
+    def _admit(self, q: Request, stream) -> bool:
+        pieces = [32 * q.ncells, 8 * q.ncells, 8 * max(q.nkeys, 1), 8 * self.max_rounds, 64]
+        got = []
+        for p in pieces:
+            a = self.arena.alloc(p)
+            if a is None:
+                for off, nb in got:
+                    self.arena.free(off, nb)
+                return False
+            got.append(a)
+        q._alloc = got
+        (co, cn), (ko, kn), (io, inn), (so, sn), (mo, mn) = got
+        cells = self.arena.view(co, cn, torch.int64)[: 4 * q.ncells].view(q.ncells, 4)
+        keys_out = self.arena.view(ko, kn, torch.int64)[: q.ncells]
+        ins = self.arena.view(io, inn, torch.int64)[: max(q.nkeys, 1)]
+        stats = self.arena.view(so, sn, torch.int64)[: self.max_rounds]
+        summ = self.arena.view(mo, mn, torch.int64)[:8]
+        desc = pk.iblt_desc(q.ncells, q.r, q.table_seed)
+        with torch.cuda.stream(stream):
+            cells.zero_()
+            if q.nkeys:
+                self.fill_keys(q, ins[: q.nkeys])
+                pk.iblt_insert(desc, cells, ins[: q.nkeys], stream=stream)
+        q._table = pk.BatchTable(desc, cells, keys_out, stats, summ)
+        return True
+
+    def _retire(self, q: Request, now: float) -> None:
+        q.done = now
+        q.summary = q._table.summary.cpu().numpy().copy()
+        if self.keep_keys:
+            listed = int(q.summary[0])
+            q.keys_out = q._table.keys[:listed].cpu().numpy().view(np.uint64).copy()
+            q.round_stats = q._table.round_stats[: int(q.summary[1])].cpu().numpy().view(np.uint64).copy()
+        for off, nb in q._alloc:
+            self.arena.free(off, nb)
+        q._alloc = []
+        q._table = None
+
+
+class ContinuousServer(_Base):
+    """Continuous batching over iblt_list_batched (see the module docstring)."""
+
+    def __init__(self, budget: int, fill_keys, max_cells: int, max_rounds: int = 256,
+                 max_inflight: int = 2, block_threads: int = 512, keep_keys: bool = False,
+                 device="cuda"):
+        super().__init__(budget, fill_keys, max_rounds, keep_keys, device)
+        self.max_cells = max_cells
+        self.max_inflight = max_inflight
+        self.block_threads = block_threads
+        self.insert_stream = torch.cuda.Stream(device=self.device)
+        self.list_streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
+        # one batched-listing workspace per in-flight launch, sized for the largest table
+        self.ws = [pk.workspace(pk.iblt_list_batched_workspace(1 << 16, max_cells), self.device)
+                   for _ in range(max_inflight)]
+        self.batches = 0
+
+    def run(self, requests: list[Request], poll_s: float = 2e-5) -> list[Request]:
+        pending = sorted(requests, key=lambda q: q.arrival)
+        waiting: list[Request] = []      # arrived, not admitted
+        ready: list[Request] = []        # inserted, not listed
+        inflight: list[tuple] = []       # (event, requests, slot, entries)
+        free_slots = list(range(self.max_inflight))
+        done: list[Request] = []
+        t0 = time.perf_counter()
+        i = 0
+        while len(done) + len(self.rejected) < len(requests):
+            now = time.perf_counter() - t0
+            while i < len(pending) and pending[i].arrival <= now:
+                waiting.append(pending[i])
+                i += 1
+            # admit in arrival order while the arena has room
+            admitted = []
+            while waiting:
+                q = waiting[0]
+                if q.footprint(self.max_rounds) > self.arena.budget:
+                    self.rejected.append(waiting.pop(0))
+                    continue
+                if not self._admit(q, self.insert_stream):
+                    break
+                q.admitted = now
+                admitted.append(waiting.pop(0))
+            if admitted:
+                ev = torch.cuda.Event()
+                ev.record(self.insert_stream)
+                for q in admitted:
+                    q._event = ev
+                ready.extend(admitted)
+            # retire finished launches
+            still = []
+            for ev, qs, slot, ent in inflight:
+                if ev.query():
+                    tnow = time.perf_counter() - t0
+                    for q in qs:
+                        self._retire(q, tnow)
+                        done.append(q)
+                    free_slots.append(slot)
+                else:
+                    still.append((ev, qs, slot, ent))
+            inflight = still
+            # launch the ready tables as one batch
+            if ready and free_slots:
+                slot = free_slots.pop()
+                s = self.list_streams[slot]
+                qs = sorted(ready, key=lambda q: -q.ncells)
+                ready = []
+                for ev in {id(q._event): q._event for q in qs}.values():
+                    s.wait_event(ev)
+                with torch.cuda.stream(s):
+                    ent = pk.batch_entries([q._table for q in qs], self.device)
+                    pk.iblt_list_batched(ent, len(qs), self.max_cells, self.max_rounds,
+                                         block_threads=self.block_threads, ws=self.ws[slot],
+                                         stream=s)
+                ev = torch.cuda.Event()
+                ev.record(s)
+                inflight.append((ev, qs, slot, ent))
+                self.batches += 1
+            if i >= len(pending) and not waiting and not ready and not inflight:
+                break
+            time.sleep(poll_s)
+        return done
+
+
+class FifoServer(_Base):
+    """Plain baseline: one request at a time, insert then iblt_list, one stream."""
+
+    def __init__(self, budget: int, fill_keys, max_rounds: int = 256, keep_keys: bool = False,
+                 device="cuda", max_cells: int = 1 << 22):
+        super().__init__(budget, fill_keys, max_rounds, keep_keys, device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.ws = pk.workspace(pk.iblt_list_workspace(pk.iblt_desc(max_cells, 3, 0)), self.device)
+
+    def run(self, requests: list[Request], poll_s: float = 2e-5) -> list[Request]:
+        pending = sorted(requests, key=lambda q: q.arrival)
+        done = []
+        t0 = time.perf_counter()
+        for q in pending:
+            while time.perf_counter() - t0 < q.arrival:
+                time.sleep(poll_s)
+            if q.footprint(self.max_rounds) > self.arena.budget or not self._admit(q, self.stream):
+                self.rejected.append(q)
+                continue
+            q.admitted = time.perf_counter() - t0
+            t = q._table
+            out = pk.ListOut(t.keys, t.round_stats, t.summary)
+            with torch.cuda.stream(self.stream):
+                pk.iblt_list(t.desc, t.cells, max_rounds=self.max_rounds, out=out, ws=self.ws,
+                             stream=self.stream)
+            self.stream.synchronize()
+            self._retire(q, time.perf_counter() - t0)
+            done.append(q)
+        return done
+
+
+def latency_stats(done: list[Request]) -> dict:
+    lat = np.array([q.done - q.arrival for q in done]) if done else np.zeros(1)
+    span = (max(q.done for q in done) - min(q.arrival for q in done)) if done else 0.0
+    return {
+        "requests": len(done),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3),
+        "req_per_s": len(done) / span if span > 0 else 0.0,
+    }

@@ -1,0 +1,63 @@
+"""GPU check of the continuous-batching server: every request's result in the
+mix equals its result served alone and the oracle's, and the HBM budget holds."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import native
+from paper_1302_7014_amd.serve import ContinuousServer, FifoServer, Request, latency_stats
+from workloads import configs, gen
+
+from gpu_helpers import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _fill(q, out):
+    out.copy_(gen.distinct_keys_torch(q.nkeys, q.key_seed, out.device))
+
+
+def _requests(count, rate, seed, lo=6, hi=14):
+    spec = configs.ServeSpec("test", log2_lo=lo, log2_hi=hi, load_lo=0.3, load_hi=1.1)
+    return [Request(i, *x) for i, x in enumerate(spec.requests(count, rate, seed))]
+
+
+def _groups(q):
+    out, off = [], 0
+    for kk in q.round_stats.tolist():
+        out.append(np.sort(q.keys_out[off: off + kk]))
+        off += kk
+    return out
+
+
+def test_mix_equals_alone_and_oracle():
+    need_gpu()
+    budget = 6 << 20  # small: arrivals must wait for space
+    mix = _requests(80, 4000.0, 11)
+    say("serve mix", len(mix))
+    srv = ContinuousServer(budget, _fill, max_cells=1 << 14, keep_keys=True)
+    done = srv.run(mix)
+    assert len(done) == len(mix) and not srv.rejected
+    assert srv.arena.peak <= budget and srv.batches >= 2
+    alone = FifoServer(budget, _fill, keep_keys=True, max_cells=1 << 14).run(_requests(80, 0.0, 11))
+    by_id = {q.rid: q for q in alone}
+    for q in done:
+        a = by_id[q.rid]
+        assert np.array_equal(q.summary[:4], a.summary[:4])
+        ga, gm = _groups(a), _groups(q)
+        assert len(ga) == len(gm) and all(np.array_equal(x, y) for x, y in zip(ga, gm))
+        k = gen.distinct_keys(q.nkeys, q.key_seed)
+        o = native.iblt_list_rounds(native.iblt_insert(q.ncells, q.r, q.table_seed, k), max_rounds=256)
+        assert int(q.summary[0]) == o.keys.size and int(q.summary[1]) == o.rounds
+        assert all(np.array_equal(x, y) for x, y in zip(gm, o.per_round()))
+    st = latency_stats(done)
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_request_over_budget_is_rejected():
+    need_gpu()
+    reqs = _requests(5, 0.0, 3)
+    big = Request(99, 0.0, 3, 1 << 20, 1000, 1, 2)
+    srv = ContinuousServer(4 << 20, _fill, max_cells=1 << 20)
+    done = srv.run(reqs + [big])
+    assert [q.rid for q in srv.rejected] == [99] and len(done) == 5

@@ -132,3 +132,35 @@ class BatchSpec:
 
 def batched_main() -> BatchSpec:
     return BatchSpec("iblt_batched_4096_r3", 4096, 3, 10.0, 20.0, 0.5, 0.8)
+
+
+@dataclass(frozen=True)
+class ServeSpec:
+    """Poisson arrivals of IBLT list requests of mixed sizes (served decoding)."""
+    name: str
+    r_choices: tuple = (3, 4)
+    log2_lo: float = 8.0
+    log2_hi: float = 22.0
+    load_lo: float = 0.4   # as a fraction of c*_{2,r}
+    load_hi: float = 0.85
+    budget_bytes: int = 64 << 30
+
+    def requests(self, count: int, rate: float, seed: int):
+        """[(arrival_s, r, ncells, nkeys, key_seed, table_seed)]; rate <= 0 = all at t=0."""
+        st = gen.stream_seed(seed, 0x7C3B2A1908F7E6D5)
+        u = gen.splitmix64(st, np.arange(5 * count, dtype=np.uint64)).reshape(count, 5)
+        unit = (u >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+        out, t = [], 0.0
+        for i in range(count):
+            if rate > 0:
+                t += -np.log(1.0 - unit[i, 0]) / rate
+            r = self.r_choices[int(unit[i, 1] * len(self.r_choices)) % len(self.r_choices)]
+            N = max(r, int(round(2.0 ** (self.log2_lo + (self.log2_hi - self.log2_lo) * unit[i, 2]))))
+            load = (self.load_lo + (self.load_hi - self.load_lo) * unit[i, 3]) * cstar(2, r)
+            ks = int(u[i, 4])
+            out.append((t, r, N, int(round(load * N)), ks, gen.table_seed(ks)))
+        return out
+
+
+def served_main() -> ServeSpec:
+    return ServeSpec("iblt_served_r34_N256-4M")

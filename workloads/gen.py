@@ -157,3 +157,26 @@ def distinct_keys(m: int, seed: int) -> np.ndarray:
 def table_seed(seed: int) -> int:
     """The hash-family seed an IBLT built for workload ``seed`` is given."""
     return stream_seed(seed, _DOMAIN_TABLE)
+
+
+def _i64(x: int) -> int:
+    """The int64 with the same bits as the 64-bit word x."""
+    x &= 0xFFFFFFFFFFFFFFFF
+    return x - (1 << 64) if x >> 63 else x
+
+
+def _srl(z, k: int):
+    """Logical right shift of an int64 torch tensor (bits as uint64)."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def distinct_keys_torch(m: int, seed: int, device):
+    """``distinct_keys(m, seed)`` computed with torch on ``device`` (int64 tensor of the
+    same bits), for harnesses that must not spend host time on key generation."""
+    import torch
+    st = stream_seed(seed, _DOMAIN_KEY)
+    z = torch.arange(1, m + 1, dtype=torch.int64, device=device)
+    z = z * _i64(int(GOLDEN)) + _i64(st)
+    z = (z ^ _srl(z, 30)) * _i64(int(_C1))
+    z = (z ^ _srl(z, 27)) * _i64(int(_C2))
+    return z ^ _srl(z, 31)
