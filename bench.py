@@ -222,16 +222,19 @@ def bench_batched(spec, reps):
             t.cells.copy_(p)
         torch.cuda.synchronize()
 
-    # capture the batched call in a graph
+    # pick the schedule on this batch, then capture the batched call in a graph
+    from paper_1302_7014_amd.autotune import tune_batched
+    sched, trials = tune_batched(tables, ent, maxc, 256, ws)
+    log(f"batched schedule {sched}")
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        pk.iblt_list_batched(ent, len(tables), maxc, 256, ws=ws)
+        pk.iblt_list_batched(ent, len(tables), maxc, 256, ws=ws, **sched)
     torch.cuda.current_stream().wait_stream(side)
     reset()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        pk.iblt_list_batched(ent, len(tables), maxc, 256, ws=ws)
+        pk.iblt_list_batched(ent, len(tables), maxc, 256, ws=ws, **sched)
     tb = Timer()
     for _ in range(reps):
         reset()
@@ -255,6 +258,7 @@ def bench_batched(spec, reps):
     return {
         "workload": spec.name, "tables": len(tables), "cells": int(sum(x[0] for x in draw)),
         "keys": nkeys, "listed": listed, "incomplete_tables": incomplete,
+        "schedule": sched, "tuner_trials": trials,
         "batched_graph_ms": bt, "plain_per_table_ms": pt, "speedup": pt / bt,
         "batched_keys_per_s": listed / (bt * 1e-3), "plain_keys_per_s": listed_plain / (pt * 1e-3),
         "listed_equal": listed == listed_plain,
@@ -278,9 +282,11 @@ def bench_serve(spec, n_cal, n_rate, warm):
     cont = ContinuousServer(spec.budget_bytes, fill, max_cells=1 << 22)
     cal = latency_stats(cont.run(reqs(n_cal, 0.0, 5)))
     lam = cal["req_per_s"]
-    out = {"workload": spec.name, "budget_gb": spec.budget_bytes / 2 ** 30,
-           "saturated_req_per_s": lam, "warmup_requests": warm, "rates": []}
     fifo = FifoServer(spec.budget_bytes, fill)
+    fifo_sat = latency_stats(fifo.run(reqs(n_cal, 0.0, 5)))["req_per_s"]
+    out = {"workload": spec.name, "budget_gb": spec.budget_bytes / 2 ** 30,
+           "small_cells": cont.small_cells, "saturated_req_per_s": lam,
+           "fifo_saturated_req_per_s": fifo_sat, "warmup_requests": warm, "rates": []}
     for i, frac in enumerate((0.3, 0.6, 0.9)):
         rate = frac * lam
         log(f"serving at {rate:.0f} req/s")
@@ -289,6 +295,7 @@ def bench_serve(spec, n_cal, n_rate, warm):
         out["rates"].append({"fraction": frac, "rate_req_per_s": rate, "continuous": c, "fifo": f})
     out["peak_budget_used_gb"] = cont.arena.peak / 2 ** 30
     out["batches"] = cont.batches
+    out["large_lane_lists"] = cont.large
     return out
 
 
@@ -346,7 +353,7 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also time every c of the n=2^24 sweep")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=1500, help="measured requests per rate")
+    ap.add_argument("--serve-requests", type=int, default=5000, help="measured requests per rate")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -391,7 +398,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_serve:
         log("served decoding")
-        extra["serve"] = bench_serve(configs.served_main(), 600, args.serve_requests, 200)
+        extra["serve"] = bench_serve(configs.served_main(), 1000, args.serve_requests, 500)
     if args.sweep:
         sw = []
         for c in configs.SWEEP_C:

@@ -200,14 +200,30 @@ peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_key
  * order of `entries` from a shared counter and list each with workgroup-wide
  * barriers only.  Sorting `entries` by decreasing ncells balances the load.
  *
+ * Two per-table schedules exist.  A table of at most `lds_max_cells` cells is
+ * read once into the workgroup's local memory (LDS), listed there with LDS
+ * atomics, and written back; a larger table is listed in place in device
+ * memory.  Both give the same results.
+ *
  *   entries       (device) ntables descriptors; every pointer in them is
  *                 device memory and every table is disjoint from the others.
  *   max_cells     >= the largest ncells among the tables.
  *   max_rounds    >= 1, for every table (round_stats hold max_rounds each).
- *   block_threads 256, 512 or 1024 threads per workgroup; 0 = 512.
+ *   sched         (host) the schedule, or NULL for the defaults (512 threads,
+ *                 lds_max_cells = IBLT_LDS_MAX_CELLS).  block_threads must be
+ *                 256, 512 or 1024 (0 = 512) and lds_max_cells at most
+ *                 IBLT_LDS_MAX_CELLS, else PEEL_EINVAL.
  *   ws            (device) ws_bytes >= iblt_list_batched_workspace().
  * Each table's summary is written as iblt_list's ([4] = 1 workgroup).
  */
+#define IBLT_LDS_MAX_CELLS 2048u
+
+typedef struct iblt_batch_schedule {
+    uint32_t block_threads;  /* threads per workgroup: 256, 512, 1024; 0 = 512 */
+    uint32_t lds_max_cells;  /* tables this small are listed in LDS; 0 = none */
+    uint32_t reserved[2];    /* 0 */
+} iblt_batch_schedule;
+
 typedef struct iblt_batch_entry {
     iblt_desc desc;
     iblt_cell *cells;      /* ncells cells, 32-byte aligned, consumed in place */
@@ -219,8 +235,9 @@ typedef struct iblt_batch_entry {
 
 size_t iblt_list_batched_workspace(uint32_t ntables, uint64_t max_cells);
 peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32_t ntables,
-                              uint64_t max_cells, uint32_t max_rounds, uint32_t block_threads,
-                              void *ws, size_t ws_bytes, void *stream);
+                              uint64_t max_cells, uint32_t max_rounds,
+                              const iblt_batch_schedule *sched, void *ws, size_t ws_bytes,
+                              void *stream);
 
 #ifdef __cplusplus
 }

@@ -65,7 +65,7 @@ def lib() -> C.CDLL:
         L.iblt_list.argtypes = [C.POINTER(IbltDesc), P, P, u64, P, u32, P, P, sz, P]
         L.iblt_list_batched_workspace.argtypes = [u32, u64]
         L.iblt_list_batched_workspace.restype = sz
-        L.iblt_list_batched.argtypes = [P, u32, u64, u32, u32, P, sz, P]
+        L.iblt_list_batched.argtypes = [P, u32, u64, u32, C.POINTER(BatchSchedule), P, sz, P]
         for f in ("hg_build", "peel_kcore", "iblt_insert", "iblt_list", "iblt_list_batched"):
             getattr(L, f).restype = C.c_int32
         _lib = L
@@ -248,10 +248,25 @@ def iblt_list_batched_workspace(ntables: int, max_cells: int) -> int:
     return int(lib().iblt_list_batched_workspace(ntables, max_cells))
 
 
+IBLT_LDS_MAX_CELLS = 2048
+
+
+class BatchSchedule(C.Structure):
+    """iblt_batch_schedule: threads per workgroup and the LDS-resident size limit."""
+    _fields_ = [("block_threads", C.c_uint32), ("lds_max_cells", C.c_uint32),
+                ("reserved", C.c_uint32 * 2)]
+
+
 def iblt_list_batched(entries: torch.Tensor, ntables: int, max_cells: int, max_rounds: int,
-                      block_threads: int = 0, ws: torch.Tensor | None = None, stream=None) -> None:
-    """List every table of a batch in one launch (entries from ``batch_entries``)."""
+                      block_threads: int = 0, lds_max_cells: int | None = None,
+                      ws: torch.Tensor | None = None, stream=None) -> None:
+    """List every table of a batch in one launch (entries from ``batch_entries``).
+
+    ``lds_max_cells``: tables of at most this many cells are listed from LDS
+    (None = the library default, IBLT_LDS_MAX_CELLS; 0 = never)."""
     if ws is None:
         ws = workspace(iblt_list_batched_workspace(ntables, max_cells), entries.device)
-    _check(lib().iblt_list_batched(_ptr(entries), ntables, max_cells, max_rounds, block_threads,
+    sched = BatchSchedule(block_threads,
+                          IBLT_LDS_MAX_CELLS if lds_max_cells is None else lds_max_cells)
+    _check(lib().iblt_list_batched(_ptr(entries), ntables, max_cells, max_rounds, C.byref(sched),
                                    _ptr(ws), ws.numel(), _stream(stream)), "iblt_list_batched")

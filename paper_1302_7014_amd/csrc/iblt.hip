@@ -22,6 +22,8 @@
 // Round 1's candidates are all cells (one dense pass, which also sums the
 // counts).  Every cell pure at the start of round t+1 went 2 -> 1 during
 // round t, so the candidate lists miss none.
+#include <type_traits>
+
 #include "common.hpp"
 #include "host.hpp"
 
@@ -458,16 +460,169 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// LDS-resident schedule for small tables: the table is read once into the
+// workgroup's local memory (structure of arrays), every round's detect and
+// apply run on it with LDS atomics, and the final cells are written back.
+// Same rounds and key sets as the in-place schedule.
+
+constexpr uint32_t kLdsCells = IBLT_LDS_MAX_CELLS;
+
+struct LdsTable {
+  int32_t cnt[kLdsCells];
+  uint64_t ks[kLdsCells];
+  uint64_t hs[kLdsCells];
+  uint16_t own[kLdsCells];   // cells whose key this round lists (at most one per cell)
+  uint16_t cand[kLdsCells];  // cells that went 2 -> 1 this round (at most once each)
+};
+
+template <int R>
+__device__ inline bool owns_lds(const Hash &h, const LdsTable &T, uint32_t c, uint32_t *bad) {
+  if (T.cnt[c] != 1) return false;
+  const uint64_t ks = T.ks[c];
+  const uint64_t hx = check_of(h, ks);
+  if (T.hs[c] != hx) {
+    *bad = 1;
+    return false;
+  }
+  const uint32_t j = subtable_of(h, c);
+#pragma unroll
+  for (int i = 0; i < R - 1; ++i) {
+    if (i >= (int)j) break;
+    const uint32_t o = cell_of(h, i, ks);
+    if (T.cnt[o] == 1 && T.ks[o] == ks && T.hs[o] == hx) return false;
+  }
+  return true;
+}
+
+template <int R, int NT>
+__device__ void list_table_lds(const Hash &h, iblt_cell *cells, uint32_t N, uint64_t *out,
+                               uint64_t out_cap, uint64_t *stats, uint32_t max_rounds,
+                               uint64_t *summary, LdsTable &T) {
+  __shared__ uint32_t s_k, s_c, s_bad, s_flags;
+  __shared__ unsigned long long s_sum;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < max_rounds; i += NT) stats[i] = 0;
+  if (tid == 0) {
+    s_k = 0;
+    s_bad = 0;
+    s_flags = 0;
+    s_sum = 0;
+  }
+  {
+    long long local = 0;
+    for (uint32_t c = tid; c < N; c += NT) {
+      int32_t cnt;
+      uint64_t ks, hs;
+      load_cell(cells + c, &cnt, &ks, &hs);
+      T.cnt[c] = cnt;
+      T.ks[c] = ks;
+      T.hs[c] = hs;
+      local += cnt;
+    }
+    __syncthreads();
+    atomicAdd(&s_sum, (unsigned long long)local);
+  }
+  uint64_t listed = 0;
+  {
+    uint32_t bad = 0;
+    for (uint32_t c = tid; c < N; c += NT) {
+      if (owns_lds<R>(h, T, c, &bad)) {
+        const uint32_t pos = atomicAdd(&s_k, 1u);
+        T.own[pos] = static_cast<uint16_t>(c);
+        if (pos < out_cap) out[pos] = T.ks[c];
+      }
+    }
+    if (bad) s_bad = 1;
+  }
+  __syncthreads();
+  uint32_t t = 1;
+  for (;; ++t) {
+    const uint32_t K = s_k;
+    if (K == 0) break;
+    if (t > max_rounds) {
+      if (tid == 0) s_flags |= PEEL_FLAG_EROUNDS;
+      break;
+    }
+    if (listed + K > out_cap) {
+      if (tid == 0) s_flags |= PEEL_FLAG_ENOSPC;
+      break;
+    }
+    if (tid == 0) {
+      stats[t - 1] = K;
+      s_c = 0;
+    }
+    __syncthreads();
+    // apply: the listed key of cell own[i] is still that cell's key_sum
+    for (uint32_t i = tid; i < K; i += NT) {
+      const uint32_t co = T.own[i];
+      const uint64_t x = T.ks[co];
+      const uint64_t hx = check_of(h, x);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint32_t c = cell_of(h, j, x);
+        if (c == co) continue;
+        const int32_t old = atomicSub(&T.cnt[c], 1);
+        atomicXor(reinterpret_cast<unsigned long long *>(&T.ks[c]), (unsigned long long)x);
+        atomicXor(reinterpret_cast<unsigned long long *>(&T.hs[c]), (unsigned long long)hx);
+        if (old == 2) T.cand[atomicAdd(&s_c, 1u)] = static_cast<uint16_t>(c);
+      }
+    }
+    __syncthreads();
+    // the owner cells held their key alone: clear them after every key was read
+    for (uint32_t i = tid; i < K; i += NT) {
+      const uint32_t co = T.own[i];
+      T.cnt[co] = 0;
+      T.ks[co] = 0;
+      T.hs[co] = 0;
+    }
+    listed += K;
+    const uint32_t nc = s_c;
+    __syncthreads();
+    if (tid == 0) s_k = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (uint32_t i = tid; i < nc; i += NT) {
+      const uint32_t c = T.cand[i];
+      if (owns_lds<R>(h, T, c, &bad)) {
+        const uint32_t pos = atomicAdd(&s_k, 1u);
+        T.own[pos] = static_cast<uint16_t>(c);
+        if (listed + pos < out_cap) out[listed + pos] = T.ks[c];
+      }
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+  }
+  for (uint32_t c = tid; c < N; c += NT) {
+    uint4 *p = reinterpret_cast<uint4 *>(cells + c);
+    const uint64_t ks = T.ks[c], hs = T.hs[c];
+    p[0] = make_uint4(static_cast<uint32_t>(T.cnt[c]), 0u, static_cast<uint32_t>(ks),
+                      static_cast<uint32_t>(ks >> 32));
+    p[1] = make_uint4(static_cast<uint32_t>(hs), static_cast<uint32_t>(hs >> 32), 0u, 0u);
+  }
+  if (tid == 0) {
+    const long long keys = (long long)s_sum / (long long)R;
+    summary[0] = listed;
+    summary[1] = t - 1 < max_rounds ? t - 1 : max_rounds;
+    summary[2] = (uint64_t)(keys - (long long)listed);
+    summary[3] = s_flags | (s_bad ? PEEL_FLAG_ECORRUPT : 0u);
+    summary[4] = 1;
+    summary[5] = summary[6] = summary[7] = 0;
+  }
+  __syncthreads();
+}
+
 struct BatchCtrl {
   uint32_t ticket;
   uint32_t pad[63];
 };
 
-template <int NT>
+template <int NT, bool LDS>
 __global__ void __launch_bounds__(NT)
     k_list_batched(const iblt_batch_entry *entries, uint32_t ntables, uint32_t max_rounds,
-                   BatchCtrl *ctrl, uint32_t *scratch, uint64_t max_cells) {
+                   BatchCtrl *ctrl, uint32_t *scratch, uint64_t max_cells, uint32_t lds_max) {
   __shared__ uint32_t s_t;
+  __shared__ typename std::conditional<LDS, LdsTable, uint32_t>::type lt;
   uint32_t *cand = scratch + (uint64_t)blockIdx.x * 2 * max_cells;
   uint32_t *own = cand + max_cells;
   for (;;) {
@@ -479,6 +634,23 @@ __global__ void __launch_bounds__(NT)
     const iblt_batch_entry e = entries[ti];
     const Hash h = make_hash(e.desc);
     const uint32_t N = static_cast<uint32_t>(e.desc.ncells);
+    if constexpr (LDS) {
+      if (N <= lds_max) {
+#define PEEL_LDS_CASE(RR) \
+  case RR: list_table_lds<RR, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, lt); break;
+        switch (e.desc.r) {
+          PEEL_LDS_CASE(2)
+          PEEL_LDS_CASE(3)
+          PEEL_LDS_CASE(4)
+          PEEL_LDS_CASE(5)
+          PEEL_LDS_CASE(6)
+          PEEL_LDS_CASE(7)
+          default: list_table_lds<8, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, lt); break;
+        }
+#undef PEEL_LDS_CASE
+        continue;
+      }
+    }
     switch (e.desc.r) {
       case 2: list_table_block<2, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
       case 3: list_table_block<3, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
@@ -637,12 +809,16 @@ extern "C" size_t iblt_list_batched_workspace(uint32_t ntables, uint64_t max_cel
 
 extern "C" peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32_t ntables,
                                          uint64_t max_cells, uint32_t max_rounds,
-                                         uint32_t block_threads, void *ws, size_t ws_bytes,
-                                         void *stream) {
+                                         const iblt_batch_schedule *sched, void *ws,
+                                         size_t ws_bytes, void *stream) {
   if ((ntables && !entries) || max_rounds == 0 || max_cells >= (1ull << 32) || !ws)
     return PEEL_EINVAL;
-  if (block_threads == 0) block_threads = 512;
-  if (block_threads != 256 && block_threads != 512 && block_threads != 1024) return PEEL_EINVAL;
+  iblt_batch_schedule sc{512u, kLdsCells, {0u, 0u}};
+  if (sched) sc = *sched;
+  if (sc.block_threads == 0) sc.block_threads = 512;
+  if (sc.block_threads != 256 && sc.block_threads != 512 && sc.block_threads != 1024)
+    return PEEL_EINVAL;
+  if (sc.lds_max_cells > kLdsCells || sc.reserved[0] || sc.reserved[1]) return PEEL_EINVAL;
   const uint32_t grid = batched_grid(ntables);
   if (ws_bytes < batched_ws_bytes(ntables, max_cells, grid)) return PEEL_ENOSPC;
   if (ntables == 0) return PEEL_OK;
@@ -650,17 +826,22 @@ extern "C" peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32
   BatchCtrl *ctrl = static_cast<BatchCtrl *>(ws);
   uint32_t *scratch = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + align_up(sizeof(BatchCtrl)));
   hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(64), 0, s, ctrl);
-  switch (block_threads) {
+  const uint32_t lm = sc.lds_max_cells;
+#define PEEL_BATCH_LAUNCH(NT, L) \
+  hipLaunchKernelGGL((k_list_batched<NT, L>), dim3(grid), dim3(NT), 0, s, entries, ntables, \
+                     max_rounds, ctrl, scratch, max_cells, lm)
+  switch (sc.block_threads) {
     case 256:
-      hipLaunchKernelGGL(k_list_batched<256>, dim3(grid), dim3(256), 0, s, entries, ntables, max_rounds, ctrl, scratch, max_cells);
+      if (lm) PEEL_BATCH_LAUNCH(256, true); else PEEL_BATCH_LAUNCH(256, false);
       break;
     case 512:
-      hipLaunchKernelGGL(k_list_batched<512>, dim3(grid), dim3(512), 0, s, entries, ntables, max_rounds, ctrl, scratch, max_cells);
+      if (lm) PEEL_BATCH_LAUNCH(512, true); else PEEL_BATCH_LAUNCH(512, false);
       break;
     default:
-      hipLaunchKernelGGL(k_list_batched<1024>, dim3(grid), dim3(1024), 0, s, entries, ntables, max_rounds, ctrl, scratch, max_cells);
+      if (lm) PEEL_BATCH_LAUNCH(1024, true); else PEEL_BATCH_LAUNCH(1024, false);
       break;
   }
+#undef PEEL_BATCH_LAUNCH
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }

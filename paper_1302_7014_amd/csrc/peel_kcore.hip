@@ -117,6 +117,9 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   __shared__ uint32_t alive[kOwnMaxE / 32];
   __shared__ uint32_t cnt[kOwnMaxT];
   __shared__ uint32_t cur[kOwnMaxT];
+  __shared__ uint32_t s_start[kOT];
+  __shared__ uint32_t s_pre[kOT];
+  __shared__ uint32_t scan_lds[kOT / kWave + 1];
   __shared__ uint32_t s_n, s_w;
 
   PeelCtrl *ctrl = a.ctrl;
@@ -175,28 +178,48 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   uint32_t t = 1;
   for (;; ++t) {
     // ---- claims: one per incidence of every vertex of F_t --------------------
+    // The incidence lists of up to kOT frontier vertices at a time are laid end
+    // to end (workgroup scan of their lengths) and walked one incidence per
+    // thread, so every thread's loads are independent of the list lengths.
     const bool over = t > a.max_rounds;
     if (!over) {
       for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
       __syncthreads();
-      for (uint32_t i = tid; i < fcnt; i += kOT) {
-        const uint32_t v = myF[i];
-        a.vr[v] = t;
-        const uint32_t p1 = a.offsets[v + 1];
-        for (uint32_t p = a.offsets[v]; p < p1; ++p) atomicAdd(&cnt[a.inc[p] / Eb], 1u);
-      }
-      __syncthreads();
-      for (uint32_t d = tid; d < T; d += kOT) {
-        const uint32_t c = cnt[d];
-        cur[d] = c ? d * Eb * R + atomicAdd(&ctrl->qh_claim[d], c) : 0u;
-      }
-      __syncthreads();
-      for (uint32_t i = tid; i < fcnt; i += kOT) {
-        const uint32_t v = myF[i];
-        const uint32_t p1 = a.offsets[v + 1];
-        for (uint32_t p = a.offsets[v]; p < p1; ++p) {
-          const uint32_t e = a.inc[p];
-          a.qclaim[atomicAdd(&cur[e / Eb], 1u)] = e;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t c0 = 0; c0 < fcnt; c0 += kOT) {
+          uint32_t st = 0, len = 0;
+          if (c0 + tid < fcnt) {
+            const uint32_t v = myF[c0 + tid];
+            st = a.offsets[v];
+            len = a.offsets[v + 1] - st;
+            if (pass == 0) a.vr[v] = t;
+          }
+          uint32_t tot;
+          const uint32_t ex = block_exclusive_scan<kOT>(len, &tot, scan_lds);
+          s_start[tid] = st;
+          s_pre[tid] = ex;
+          __syncthreads();
+          for (uint32_t j = tid; j < tot; j += kOT) {
+            // the last list whose start is <= j holds incidence j
+            uint32_t lo = 0, hi = kOT;
+            while (hi - lo > 1) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (s_pre[mid] <= j) lo = mid; else hi = mid;
+            }
+            const uint32_t e = a.inc[s_start[lo] + (j - s_pre[lo])];
+            if (pass == 0)
+              atomicAdd(&cnt[e / Eb], 1u);
+            else
+              a.qclaim[atomicAdd(&cur[e / Eb], 1u)] = e;
+          }
+          __syncthreads();
+        }
+        if (pass == 0) {
+          for (uint32_t d = tid; d < T; d += kOT) {
+            const uint32_t c = cnt[d];
+            cur[d] = c ? d * Eb * R + atomicAdd(&ctrl->qh_claim[d], c) : 0u;
+          }
+          __syncthreads();
         }
       }
     }

@@ -8,10 +8,14 @@ first served as arena space frees up, and runs the GPU as a pipeline:
   keys are produced on the device by the caller's ``fill_keys`` and inserted
   with ``iblt_insert`` on the insert stream (this stands for receiving the
   table), overlapping whatever listing is running;
-* listing: every table inserted and not yet listed is listed in one
-  ``iblt_list_batched`` launch on a list stream; up to ``max_inflight`` such
-  launches run at once, so a request that arrives during a long batch does not
-  wait for it to end;
+* listing, routed by table size: a table of more than ``small_cells`` cells is
+  listed alone by ``iblt_list`` (every CU that is free takes part) on the large
+  lane's stream, as soon as its insert is done; the small tables that are
+  inserted and not yet listed are listed together in one
+  ``iblt_list_batched`` launch (one workgroup per table) on a small-lane
+  stream, up to ``max_inflight`` such launches at once.  One workgroup lists a
+  small table about as fast as the whole chip does (the chip's run is bound by
+  its per-round barriers), so small tables cost the large lane nothing;
 * retirement: when a launch's completion event fires, its requests complete,
   their arena space is freed and their results (the summary) are kept.
 
@@ -159,27 +163,46 @@ class _Base:
 
 
 class ContinuousServer(_Base):
-    """Continuous batching over iblt_list_batched (see the module docstring)."""
+    """Continuous batching with size routing (see the module docstring)."""
 
     def __init__(self, budget: int, fill_keys, max_cells: int, max_rounds: int = 256,
-                 max_inflight: int = 2, block_threads: int = 512, keep_keys: bool = False,
-                 device="cuda"):
+                 max_inflight: int = 2, block_threads: int = 512, small_cells: int = 1 << 12,
+                 keep_keys: bool = False, device="cuda"):
         super().__init__(budget, fill_keys, max_rounds, keep_keys, device)
         self.max_cells = max_cells
         self.max_inflight = max_inflight
         self.block_threads = block_threads
+        self.small_cells = small_cells
         self.insert_stream = torch.cuda.Stream(device=self.device)
         self.list_streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
-        # one batched-listing workspace per in-flight launch, sized for the largest table
-        self.ws = [pk.workspace(pk.iblt_list_batched_workspace(1 << 16, max_cells), self.device)
-                   for _ in range(max_inflight)]
+        self.large_stream = torch.cuda.Stream(device=self.device)
+        # one batched-listing workspace per in-flight launch, sized for the largest small table
+        self.ws = [pk.workspace(pk.iblt_list_batched_workspace(1 << 16, min(small_cells, max_cells)),
+                                self.device) for _ in range(max_inflight)]
+        self.large_ws = pk.workspace(pk.iblt_list_workspace(pk.iblt_desc(max_cells, 3, 0)),
+                                     self.device)
         self.batches = 0
+        self.large = 0
+
+    def _list_large(self, q: Request) -> torch.cuda.Event:
+        s = self.large_stream
+        s.wait_event(q._event)
+        t = q._table
+        with torch.cuda.stream(s):
+            pk.iblt_list(t.desc, t.cells, max_rounds=self.max_rounds,
+                         out=pk.ListOut(t.keys, t.round_stats, t.summary), ws=self.large_ws,
+                         stream=s)
+        ev = torch.cuda.Event()
+        ev.record(s)
+        self.large += 1
+        return ev
 
     def run(self, requests: list[Request], poll_s: float = 2e-5) -> list[Request]:
         pending = sorted(requests, key=lambda q: q.arrival)
         waiting: list[Request] = []      # arrived, not admitted
-        ready: list[Request] = []        # inserted, not listed
-        inflight: list[tuple] = []       # (event, requests, slot, entries)
+        ready: list[Request] = []        # small tables inserted, not listed
+        inflight: list[tuple] = []       # (event, requests, slot, entries) of batched launches
+        large: list[tuple] = []          # (event, request) in launch order on the large lane
         free_slots = list(range(self.max_inflight))
         done: list[Request] = []
         t0 = time.perf_counter()
@@ -205,8 +228,15 @@ class ContinuousServer(_Base):
                 ev.record(self.insert_stream)
                 for q in admitted:
                     q._event = ev
-                ready.extend(admitted)
-            # retire finished launches
+                    if q.ncells > self.small_cells:
+                        large.append((self._list_large(q), q))
+                    else:
+                        ready.append(q)
+            # retire finished work: the large lane completes in launch order
+            while large and large[0][0].query():
+                q = large.pop(0)[1]
+                self._retire(q, time.perf_counter() - t0)
+                done.append(q)
             still = []
             for ev, qs, slot, ent in inflight:
                 if ev.query():
@@ -218,7 +248,7 @@ class ContinuousServer(_Base):
                 else:
                     still.append((ev, qs, slot, ent))
             inflight = still
-            # launch the ready tables as one batch
+            # launch the ready small tables as one batch
             if ready and free_slots:
                 slot = free_slots.pop()
                 s = self.list_streams[slot]
@@ -228,14 +258,14 @@ class ContinuousServer(_Base):
                     s.wait_event(ev)
                 with torch.cuda.stream(s):
                     ent = pk.batch_entries([q._table for q in qs], self.device)
-                    pk.iblt_list_batched(ent, len(qs), self.max_cells, self.max_rounds,
+                    pk.iblt_list_batched(ent, len(qs), max(q.ncells for q in qs), self.max_rounds,
                                          block_threads=self.block_threads, ws=self.ws[slot],
                                          stream=s)
                 ev = torch.cuda.Event()
                 ev.record(s)
                 inflight.append((ev, qs, slot, ent))
                 self.batches += 1
-            if i >= len(pending) and not waiting and not ready and not inflight:
+            if i >= len(pending) and not waiting and not ready and not inflight and not large:
                 break
             time.sleep(poll_s)
         return done

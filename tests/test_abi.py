@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_version_and_strerror(L):
-    assert L.peel_abi_version() == 1
+    assert L.peel_abi_version() == 2
     for code in range(-6, 1):
         assert L.peel_strerror(code)
     assert L.peel_strerror(-99) == b"unknown status"
@@ -68,6 +68,21 @@ def test_argument_errors_are_reported_on_the_host(L):
     d = pk.iblt_desc(100, 3, 1)
     assert L.iblt_list(C.byref(d), dummy, dummy, 10, dummy, 8, dummy, dummy, 1, None) == pk.binding.PEEL_ENOSPC
     assert L.iblt_list(C.byref(d), dummy, dummy, 10, dummy, 0, dummy, dummy, 1 << 20, None) == pk.binding.PEEL_EINVAL
+
+
+def test_batched_schedule_is_checked_on_the_host(L):
+    src = open(os.path.join(ROOT, "include", "peel.h")).read()
+    assert int(re.search(r"#define IBLT_LDS_MAX_CELLS (\d+)u", src).group(1)) == pk.IBLT_LDS_MAX_CELLS
+    assert C.sizeof(pk.BatchSchedule) == 16
+    P = C.c_void_p
+    dummy = P(0x1000)
+    for bt, lds in [(128, 0), (300, 0), (512, pk.IBLT_LDS_MAX_CELLS + 1)]:
+        s = pk.BatchSchedule(bt, lds)
+        assert L.iblt_list_batched(dummy, 4, 1000, 8, C.byref(s), dummy, 1 << 30, None) == pk.binding.PEEL_EINVAL
+    s = pk.BatchSchedule(512, 0)
+    s.reserved[0] = 1
+    assert L.iblt_list_batched(dummy, 4, 1000, 8, C.byref(s), dummy, 1 << 30, None) == pk.binding.PEEL_EINVAL
+    assert L.iblt_list_batched(dummy, 4, 1000, 0, None, dummy, 1 << 30, None) == pk.binding.PEEL_EINVAL
 
 
 def test_oracle_and_library_share_no_code():

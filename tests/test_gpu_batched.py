@@ -72,18 +72,67 @@ def _specs(n, seed, lo=6, hi=14, rs=(2, 3, 4, 5)):
     return out
 
 
+@pytest.mark.parametrize("lds", [0, pk.IBLT_LDS_MAX_CELLS])
 @pytest.mark.parametrize("threads", [256, 512, 1024])
-def test_batched_matches_oracle(threads):
+def test_batched_matches_oracle(threads, lds):
+    # tables of 2^6 .. 2^14 cells: with lds on, those of <= 2048 cells are listed in LDS
     need_gpu()
     specs = _specs(48, 3)
     specs.sort(key=lambda x: -x[0])
     tables, keys, _ = _make_tables(specs, 256)
     ent = pk.batch_entries(tables, "cuda")
-    say("batched", len(tables), "threads", threads)
-    pk.iblt_list_batched(ent, len(tables), max(x[0] for x in specs), 256, block_threads=threads)
+    say("batched", len(tables), "threads", threads, "lds", lds)
+    pk.iblt_list_batched(ent, len(tables), max(x[0] for x in specs), 256, block_threads=threads,
+                         lds_max_cells=lds)
     torch.cuda.synchronize()
     for t, k in zip(tables, keys):
         _check_against_oracle(t, k, 256)
+
+
+@pytest.mark.parametrize("threads", [256, 1024])
+def test_lds_schedule_edges(threads):
+    # LDS-resident tables at the size limit and around it, above threshold (a core
+    # remains), a tiny round limit, a tiny output capacity and a corrupt cell.
+    need_gpu()
+    L = pk.IBLT_LDS_MAX_CELLS
+    specs = [(L, 3, int(0.80 * L), 11), (L, 4, int(0.90 * L), 12), (L + 1, 3, int(0.7 * L), 13),
+             (L - 1, 5, int(0.6 * L), 14), (L, 2, int(0.45 * L), 15), (777, 3, 600, 16),
+             (3, 3, 1, 17), (4, 4, 0, 18), (L, 3, int(0.75 * L), 19), (L, 3, int(0.7 * L), 20)]
+    tables, keys, _ = _make_tables(specs, 64)
+    tables[-1] = pk.batch_table(tables[-1].desc, tables[-1].cells, 64, out_cap=100)
+    # corrupt one count-1 cell of table 5 (its checksum no longer matches)
+    o5 = native.iblt_insert(specs[5][0], 3, gen.table_seed(specs[5][3]), keys[5])
+    c = int(np.flatnonzero(o5.count == 1)[0])
+    tables[5].cells[c, 2] ^= 1
+    ent = pk.batch_entries(tables, "cuda")
+    say("lds edges", threads)
+    pk.iblt_list_batched(ent, len(tables), L + 1, 64, block_threads=threads, lds_max_cells=L)
+    torch.cuda.synchronize()
+    for i, (t, k) in enumerate(zip(tables, keys)):
+        if i == 5:
+            o5.hash_sum[c] ^= np.uint64(1)
+            o = native.iblt_list_rounds(o5, max_rounds=64)
+            s, K, groups = _result(t)
+            assert o.corrupt and int(s[3]) & 0x8
+            assert np.array_equal(K, o.K)
+            for a, b in zip(groups, o.per_round()):
+                assert np.array_equal(a, b)
+            count, ksum, hsum, ok = table_to_numpy(t.cells)
+            assert np.array_equal(count, o5.count) and np.array_equal(ksum, o5.key_sum)
+            assert np.array_equal(hsum, o5.hash_sum)
+            continue
+        _check_against_oracle(t, k, 64)
+    assert int(tables[-1].summary[3]) & 0x4   # ENOSPC
+    # a round limit of 3 for a batch of LDS-resident and in-place tables
+    specs = [(L, 3, int(0.78 * L), 21), (L + 64, 3, int(0.78 * L), 22), (1500, 4, 1000, 23)]
+    tables, keys, _ = _make_tables(specs, 3)
+    ent = pk.batch_entries(tables, "cuda")
+    say("lds round limit", threads)
+    pk.iblt_list_batched(ent, len(tables), L + 64, 3, block_threads=threads, lds_max_cells=L)
+    torch.cuda.synchronize()
+    for t, k in zip(tables, keys):
+        _check_against_oracle(t, k, 3)
+        assert int(t.summary[3]) & 0x2   # EROUNDS
 
 
 def test_batched_equals_each_table_alone():

@@ -38,7 +38,7 @@ def test_mix_equals_alone_and_oracle():
     srv = ContinuousServer(budget, _fill, max_cells=1 << 14, keep_keys=True)
     done = srv.run(mix)
     assert len(done) == len(mix) and not srv.rejected
-    assert srv.arena.peak <= budget and srv.batches >= 2
+    assert srv.arena.peak <= budget and srv.batches >= 2 and srv.large >= 1
     alone = FifoServer(budget, _fill, keep_keys=True, max_cells=1 << 14).run(_requests(80, 0.0, 11))
     by_id = {q.rid: q for q in alone}
     for q in done:
