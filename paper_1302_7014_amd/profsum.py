@@ -4,7 +4,9 @@
         per-kernel calls / average / total time from a --kernel-trace --stats run
         (the rocpd database or the *_kernel_stats.csv file it wrote).
     python -m paper_1302_7014_amd.profsum pmc <rocprof_dir> <COUNTER> [--match REGEX]
-        per-kernel average of a --pmc counter (*_counter_collection.csv).
+        per-kernel average of a --pmc counter (counter_collection CSV or rocpd database).
+    python -m paper_1302_7014_amd.profsum traffic <fetch> <write> <copy_fetch> <copy_write>
+        HBM bytes per launch from FETCH_SIZE / WRITE_SIZE runs, calibrated on a plain copy.
 
 Only reads files; prints a Markdown table.
 """
@@ -48,15 +50,48 @@ def kernel_stats(path: str) -> list[tuple[str, int, float, float]]:
 
 
 def pmc_means(path: str, counter: str) -> dict[str, tuple[int, float]]:
-    """{kernel: (dispatches, mean counter value per dispatch)} from counter_collection CSVs."""
+    """{kernel: (dispatches, mean counter value per dispatch)} from the counter_collection
+    CSVs or the rocpd database of a --pmc run."""
     acc = defaultdict(lambda: defaultdict(float))
-    for fn in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+    csvs = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    for fn in csvs:
         with open(fn) as f:
             for r in csv.DictReader(f):
                 if r.get("Counter_Name") != counter:
                     continue
                 acc[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    if not csvs:
+        for fn in glob.glob(os.path.join(path, "**", "*.db"), recursive=True):
+            db = sqlite3.connect(fn)
+            q = "select kernel_name, dispatch_id, value from counters_collection where counter_name = ?"
+            for name, disp, val in db.execute(q, (counter,)):
+                acc[name][disp] += float(val)
     return {k: (len(v), sum(v.values()) / len(v)) for k, v in acc.items() if v}
+
+
+def traffic(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str,
+            copy_bytes: int, pattern: str) -> dict:
+    """HBM bytes per launch of the kernels matching ``pattern``: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by bytes / counter for a plain copy of ``copy_bytes``."""
+    pat = re.compile(pattern)
+
+    def copy_factor(d, counter):
+        vals = [mean for name, (_, mean) in pmc_means(d, counter).items() if "copyBuffer" in name]
+        return copy_bytes / (vals[0] * 1024.0)
+
+    ff = copy_factor(copy_fetch_dir, "FETCH_SIZE")
+    wf = copy_factor(copy_write_dir, "WRITE_SIZE")
+    out = {"fetch_factor": ff, "write_factor": wf, "kernels": {}}
+    fetch = pmc_means(fetch_dir, "FETCH_SIZE")
+    write = pmc_means(write_dir, "WRITE_SIZE")
+    for name in sorted(set(fetch) & set(write)):
+        if not pat.search(name):
+            continue
+        fb = fetch[name][1] * 1024.0 * ff
+        wb = write[name][1] * 1024.0 * wf
+        out["kernels"][_short(name)] = {"fetch_bytes": fb, "write_bytes": wb,
+                                        "bytes_per_launch": fb + wb}
+    return out
 
 
 def main() -> None:
@@ -69,7 +104,17 @@ def main() -> None:
     p.add_argument("path")
     p.add_argument("counter")
     p.add_argument("--match", default="")
+    t = sub.add_parser("traffic")
+    for arg in ("fetch_dir", "write_dir", "copy_fetch_dir", "copy_write_dir"):
+        t.add_argument(arg)
+    t.add_argument("--copy-bytes", type=int, default=1 << 30)
+    t.add_argument("--match", default="")
     a = ap.parse_args()
+    if a.cmd == "traffic":
+        import json
+        print(json.dumps(traffic(a.fetch_dir, a.write_dir, a.copy_fetch_dir, a.copy_write_dir,
+                                 a.copy_bytes, a.match), indent=1))
+        return
     pat = re.compile(a.match) if a.match else None
     if a.cmd == "kernels":
         print("| kernel | calls | average (us) | total (us) |")
