@@ -38,6 +38,19 @@ __device__ inline uint32_t lanes_below(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
+// Gives every active lane with `pred` its own slot of a list whose length is
+// *counter, with one atomic per wave; the result is meaningful only where pred
+// holds.  Every active lane of the wave calls it.
+__device__ inline uint32_t wave_append(bool pred, uint32_t *counter) {
+  const uint64_t bal = __ballot(pred);
+  if (bal == 0) return 0;
+  const uint32_t leader = static_cast<uint32_t>(__builtin_ctzll(bal));
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, static_cast<uint32_t>(__popcll(bal)));
+  base = __shfl(base, leader, kWave);
+  return base + lanes_below(bal);
+}
+
 __device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
   const uint32_t lane = lane_id();
 #pragma unroll

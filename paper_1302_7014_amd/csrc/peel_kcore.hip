@@ -60,8 +60,11 @@ constexpr int kOT = 1024;             // threads per owner workgroup
 constexpr uint32_t kOwnMaxV = 98304;  // owned vertices (LDS degree bytes)
 constexpr uint32_t kOwnMaxE = 131072; // owned edges (LDS alive bits)
 constexpr uint32_t kOwnMaxT = 1024;   // owner workgroups (LDS per-destination counters)
+constexpr uint64_t kDenseRatio = 32;  // dense round when |F_{t-1}| * 32 >= alive edges
+constexpr uint32_t kNoVertex = 0xffffffffu;
 
 enum : uint32_t { kModeUndecided = 0, kModeOwnerDone = 1, kModeGlobal = 2 };
+enum : uint32_t { kRoundsAuto = 0, kRoundsDense = 1, kRoundsSparse = 2 };
 
 struct PeelCtrl {
   SumBar bar;          // owner engine barrier
@@ -93,6 +96,7 @@ struct PeelArgs {
   uint32_t *qclaim;  // owner engine: R * (m + grid) claim slots
   uint32_t *qdec;    // owner engine: R * m decrement slots, laid out by the CSR offsets
   uint32_t *stage;   // owner engine: R * (m + grid) rows of the edges won this round
+  uint32_t *fbits;   // owner engine: F_t as a bitmap over the vertices (dense rounds)
   PeelCtrl *ctrl;
   uint64_t m;
   uint64_t limit;
@@ -101,6 +105,7 @@ struct PeelArgs {
   uint32_t k;
   uint32_t max_rounds;
   uint32_t force_global;  // PEEL_ENGINE=global: skip the owner engine (testing)
+  uint32_t round_policy;  // PEEL_ROUNDS=dense|sparse: one kind of owner round only (testing)
 };
 
 __global__ void k_peel_init(PeelCtrl *ctrl) {
@@ -120,13 +125,15 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   __shared__ uint32_t s_start[kOT];
   __shared__ uint32_t s_pre[kOT];
   __shared__ uint32_t scan_lds[kOT / kWave + 1];
+  __shared__ uint32_t fbl[kOwnMaxV / 32];  // dense rounds: this workgroup's slice of F_t
   __shared__ uint32_t s_n, s_w;
 
   PeelCtrl *ctrl = a.ctrl;
   uint32_t slot, T;
   if (!team_join(&ctrl->team_own, a.quiet, a.limit, &slot, &T)) return;
   const uint32_t n = a.n;
-  const uint32_t Vb = (n + T - 1) / T;
+  // vertex ranges start on 32-vertex boundaries, so bitmap slices do not share words
+  const uint32_t Vb = ((n + T - 1) / T + 31u) & ~31u;
   const uint64_t m = a.m;
   const uint32_t Eb = m ? (uint32_t)((m + T - 1) / T) : 1u;
   if (a.force_global || T > kOwnMaxT || Vb > kOwnMaxV || Eb > kOwnMaxE) {
@@ -175,14 +182,45 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
 
   uint32_t epoch = 0;
   uint64_t removed = 0;
+  uint64_t alive_m = m;  // edges alive at the start of the round
+  uint64_t prev_v = 0;   // |F_{t-1}|
   uint32_t t = 1;
   for (;; ++t) {
-    // ---- claims: one per incidence of every vertex of F_t --------------------
-    // The incidence lists of up to kOT frontier vertices at a time are laid end
-    // to end (workgroup scan of their lengths) and walked one incidence per
-    // thread, so every thread's loads are independent of the list lengths.
     const bool over = t > a.max_rounds;
-    if (!over) {
+    // Two ways to find the edges that die in round t.  Dense: every edge owner
+    // streams the rows of its alive edges and tests their slots against F_t,
+    // published as a bitmap (n bits, which stays in L2).  Sparse: every vertex
+    // of F_t sends a claim for each incident edge to the edge's owner (random
+    // reads of the CSR, about 512 bytes per frontier vertex against 16 bytes
+    // per alive edge for the scan).  Every workgroup takes the same decision
+    // from the same global counts.
+    const bool dense = a.round_policy == kRoundsAuto ? (t == 1 || prev_v * kDenseRatio >= alive_m)
+                                                      : a.round_policy == kRoundsDense;
+    if (!over && dense) {
+      // ---- dense: publish F_t; its vertices leave with every edge they hold,
+      // so their degrees go to 0 now and the edge scan sends them no decrement
+      for (uint32_t w = tid; w < Vb / 32; w += kOT) fbl[w] = 0;
+      __syncthreads();
+      for (uint32_t i = tid; i < fcnt; i += kOT) {
+        const uint32_t v = myF[i];
+        const uint32_t lv = v - v0;
+        a.vr[v] = t;
+        atomicOr(&fbl[lv >> 5], 1u << (lv & 31));
+        const uint32_t sh = 8 * (lv & 3);
+        if (((deg8[lv >> 2] >> sh) & 255u) == 255u)
+          a.deg[v] = 0;
+        else
+          atomicAnd(&deg8[lv >> 2], ~(255u << sh));
+      }
+      __syncthreads();
+      for (uint32_t w = tid; w < (v1 - v0 + 31) / 32; w += kOT) a.fbits[v0 / 32 + w] = fbl[w];
+    }
+    // ---- sparse: one claim per incidence of every vertex of F_t that still
+    // holds an edge.  The incidence lists of up to kOT frontier vertices at a
+    // time are laid end to end (workgroup scan of their lengths) and walked one
+    // incidence per thread, so every thread's loads are independent of the
+    // list lengths.
+    if (!over && !dense) {
       for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
       __syncthreads();
       for (int pass = 0; pass < 2; ++pass) {
@@ -190,9 +228,13 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
           uint32_t st = 0, len = 0;
           if (c0 + tid < fcnt) {
             const uint32_t v = myF[c0 + tid];
-            st = a.offsets[v];
-            len = a.offsets[v + 1] - st;
+            const uint32_t lv = v - v0;
+            const uint32_t d8 = (deg8[lv >> 2] >> (8 * (lv & 3))) & 255u;
             if (pass == 0) a.vr[v] = t;
+            if (d8 != 0) {  // a vertex of degree 0 holds no alive edge
+              st = a.offsets[v];
+              len = a.offsets[v + 1] - st;
+            }
           }
           uint32_t tot;
           const uint32_t ex = block_exclusive_scan<kOT>(len, &tot, scan_lds);
@@ -234,14 +276,60 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     removed += vt;
     if (slot == 0 && tid == 0) a.stats[2ull * (t - 1)] = vt;
 
-    // ---- edge owners: claimed edges die once; decrements to every slot -------
+    // ---- edge owners: the edges of F_t die once; decrements to their slots ---
     if (tid == 0) {
-      s_n = ctrl->qh_claim[slot];
-      ctrl->qh_claim[slot] = 0;
+      s_n = dense ? 0u : ctrl->qh_claim[slot];
+      if (!dense) ctrl->qh_claim[slot] = 0;
       s_w = 0;
     }
     for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
     __syncthreads();
+    if (dense) {
+      constexpr int kOU = R <= 4 ? 4 : 2;  // edges per thread whose loads are in flight
+      // Scan my alive edges in order (coalesced rows), kOU per thread at a time
+      // so that their loads overlap.  A dying edge's slots in F_t are replaced
+      // by kNoVertex in the staged row: those vertices are already at degree 0.
+      const uint32_t nE = (uint32_t)(e1 - e0);
+      for (uint32_t b0 = 0; b0 < nE; b0 += kOU * kOT) {
+        uint32_t ids[kOU][R];
+        bool live[kOU];
+#pragma unroll
+        for (int u = 0; u < kOU; ++u) {
+          const uint32_t le = b0 + u * kOT + tid;
+          live[u] = le < nE && ((alive[le >> 5] >> (le & 31)) & 1u);
+          if (live[u]) {
+            const uint32_t *row = a.edges + (e0 + le) * R;
+#pragma unroll
+            for (int j = 0; j < R; ++j) ids[u][j] = row[j];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kOU; ++u) {
+          const uint32_t le = b0 + u * kOT + tid;
+          bool die = false;
+          if (live[u]) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+              const uint32_t x = ids[u][j];
+              if (x < n && ((a.fbits[x >> 5] >> (x & 31)) & 1u)) {
+                die = true;
+                ids[u][j] = kNoVertex;
+              }
+            }
+          }
+          const uint32_t w = wave_append(die, &s_w);
+          if (die) {
+            atomicAnd(&alive[le >> 5], ~(1u << (le & 31)));
+            a.er[e0 + le] = t;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+              myStage[(uint64_t)w * R + j] = ids[u][j];
+              if (ids[u][j] < n) atomicAdd(&cnt[ids[u][j] / Vb], 1u);
+            }
+          }
+        }
+      }
+    }
     const uint32_t nclaims = s_n;
     for (uint32_t i = tid; i < nclaims; i += kOT) {
       const uint32_t e = myClaims[i];
@@ -276,6 +364,8 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     uint64_t et;
     if (!sum_barrier(&ctrl->bar, T, slot, won, &epoch, a.limit, &et, ctrl->stamp)) return;
     if (slot == 0 && tid == 0) a.stats[2ull * (t - 1) + 1] = et;
+    alive_m -= et;
+    prev_v = vt;
 
     // ---- vertex owners: apply decrements, collect F_{t+1} --------------------
     if (tid == 0) {
@@ -457,7 +547,7 @@ __global__ void k_peel_finish(const PeelCtrl *ctrl, const uint64_t *stats, uint3
 }
 
 struct Layout {
-  size_t ctrl, fa, fb, qclaim, qdec, stage, total;
+  size_t ctrl, fa, fb, qclaim, qdec, stage, fbits, total;
 };
 
 Layout layout(uint32_t n, uint64_t m, uint32_t r) {
@@ -469,7 +559,8 @@ Layout layout(uint32_t n, uint64_t m, uint32_t r) {
   L.qclaim = align_up((size_t)r * (m + g) * 4);
   L.qdec = align_up((size_t)r * m * 4 + 4);
   L.stage = align_up((size_t)r * (m + g) * 4);
-  L.total = L.ctrl + L.fa + L.fb + L.qclaim + L.qdec + L.stage;
+  L.fbits = align_up(((size_t)n + 31) / 32 * 4 + 4);
+  L.total = L.ctrl + L.fa + L.fb + L.qclaim + L.qdec + L.stage + L.fbits;
   return L;
 }
 
@@ -530,6 +621,8 @@ extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r,
   a.qdec = reinterpret_cast<uint32_t *>(base);
   base += L.qdec;
   a.stage = reinterpret_cast<uint32_t *>(base);
+  base += L.stage;
+  a.fbits = reinterpret_cast<uint32_t *>(base);
   a.edges = edges;
   a.offsets = offsets;
   a.inc = inc;
@@ -545,6 +638,11 @@ extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r,
   a.quiet = device_info().team_quiet_ticks;
   const char *engine = std::getenv("PEEL_ENGINE");
   a.force_global = (engine && std::strcmp(engine, "global") == 0) ? 1u : 0u;
+  const char *rounds = std::getenv("PEEL_ROUNDS");
+  a.round_policy = !rounds ? kRoundsAuto
+                   : std::strcmp(rounds, "dense") == 0  ? kRoundsDense
+                   : std::strcmp(rounds, "sparse") == 0 ? kRoundsSparse
+                                                         : kRoundsAuto;
 
   hipLaunchKernelGGL(k_peel_init, dim3(1), dim3(256), 0, s, a.ctrl);
   PEEL_HIP_TRY(hipGetLastError());

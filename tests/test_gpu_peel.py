@@ -4,6 +4,8 @@ Every comparison is exact: vertex and edge removal rounds, per-round vertex and
 edge counts, round counts, final degrees and the core size.  The CSR is
 compared as per-vertex sorted edge lists (the order inside a list is free).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -43,7 +45,18 @@ def _check_against_oracle(n, edges, k, res, max_rounds=1 << 20):
     return o
 
 
-def test_small_hypergraphs_bit_exact():
+@pytest.fixture(params=["auto", "dense", "sparse"])
+def rounds(request, monkeypatch):
+    """Which rounds the owner engine runs: chosen per round (auto), or all dense
+    (edge scan against the frontier bitmap), or all sparse (claims over the CSR)."""
+    if request.param == "auto":
+        monkeypatch.delenv("PEEL_ROUNDS", raising=False)
+    else:
+        monkeypatch.setenv("PEEL_ROUNDS", request.param)
+    return request.param
+
+
+def test_small_hypergraphs_bit_exact(rounds):
     need_gpu()
     rng = np.random.default_rng(7)
     for i in range(40):
@@ -52,14 +65,14 @@ def test_small_hypergraphs_bit_exact():
         n = int(rng.integers(r, 3000))
         m = int(rng.integers(0, 3 * n))
         e = rng.integers(0, n, size=(m, r)).astype(np.uint32)
-        say("small", i, n, m, r, k)
+        say("small", rounds, i, n, m, r, k)
         res = gpu_peel(n, e, k)
         assert res["flags"] == 0
         _check_csr(n, e, res)
         _check_against_oracle(n, e, k, res)
 
 
-def test_degenerate_inputs():
+def test_degenerate_inputs(rounds):
     need_gpu()
     cases = [
         (1, 2, np.zeros((0, 3), np.uint32)),                       # one vertex, no edges
@@ -72,7 +85,7 @@ def test_degenerate_inputs():
         (8, 2, np.array([[j] * 8 for j in range(8)], np.uint32)),  # r = 8, loops
     ]
     for n, k, e in cases:
-        say("degenerate", n, k, e.shape)
+        say("degenerate", rounds, n, k, e.shape)
         res = gpu_peel(n, e, k)
         _check_csr(n, e, res)
         _check_against_oracle(n, e, k, res)
@@ -91,22 +104,22 @@ def test_config_kcore_small_seeds():
 
 @pytest.mark.parametrize("r,k,c", [(3, 2, 0.9), (4, 2, 0.7), (4, 2, 0.85), (3, 3, 1.4),
                                    (3, 3, 1.7), (2, 3, 1.2), (5, 2, 0.6), (6, 4, 2.0)])
-def test_medium_models_bit_exact(r, k, c):
+def test_medium_models_bit_exact(r, k, c, rounds):
     need_gpu()
     n = (1 << 18) + 12345  # several tiles and a ragged tail
     for model in ("partitioned", "gnm"):
         e = (gen.partitioned_edges if model == "partitioned" else gen.gnm_edges)(n, int(c * n), r, 11)
-        say("medium", model, n, r, k, c)
+        say("medium", rounds, model, n, r, k, c)
         res = gpu_peel(n, e, k)
         _check_against_oracle(n, e, k, res)
 
 
-def test_round_limit_leaves_consistent_state():
+def test_round_limit_leaves_consistent_state(rounds):
     need_gpu()
     n = 1 << 16
     e = gen.partitioned_edges(n, int(0.7 * n), 4, 5)
     for cap in (1, 3, 7):
-        say("max_rounds", cap)
+        say("max_rounds", rounds, cap)
         res = gpu_peel(n, e, 2, max_rounds=cap)
         o = native.peel_rounds(n, e, 2, max_rounds=cap)
         assert o.status == native.EROUNDS and res["flags"] & 0x2
@@ -146,7 +159,7 @@ def test_full_size_sweep_r4_n16M(c):
     need_gpu()
     spec = configs.kcore_sweep(c)
     e = spec.edges(1)
-    say(spec.name)
+    say(spec.name, "rounds", os.environ.get("PEEL_ROUNDS", "auto"))
     res = gpu_peel(spec.n, e, spec.k)
     assert res["flags"] == 0
     _check_against_oracle(spec.n, e, spec.k, res)
@@ -154,6 +167,19 @@ def test_full_size_sweep_r4_n16M(c):
         assert certify.peel_certificate(spec.n, e, spec.k, res["vertex_round"], res["edge_round"],
                                         res["deg"], res["V"], res["E"], res["rounds"],
                                         res["edge_rounds"]) == []
+
+
+@pytest.mark.parametrize("c,mode", [(0.70, "sparse"), (0.85, "dense")])
+def test_full_size_forced_round_kind(c, mode, monkeypatch):
+    # every round of one kind at full size: both kinds give the oracle's answer
+    need_gpu()
+    monkeypatch.setenv("PEEL_ROUNDS", mode)
+    spec = configs.kcore_sweep(c)
+    e = spec.edges(1)
+    say(spec.name, "rounds", mode)
+    res = gpu_peel(spec.n, e, spec.k)
+    assert res["flags"] == 0
+    _check_against_oracle(spec.n, e, spec.k, res)
 
 
 @pytest.mark.parametrize("which", ["lo", "hi"])
