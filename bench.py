@@ -69,25 +69,29 @@ def iblt_list_bytes(N, r, listed):
 
 
 class Timer:
-    """Accumulates HIP-event durations of calls made on the current stream."""
+    """HIP-event durations of calls made on the current stream (the stream the
+    library launches on).  Recording never synchronises; collect() does, once."""
 
     def __init__(self):
         self.ms = []
+        self._pending = []
 
     def __enter__(self):
-        self.a = torch.cuda.Event(enable_timing=True)
-        self.b = torch.cuda.Event(enable_timing=True)
-        self.a.record()
+        a = torch.cuda.Event(enable_timing=True)
+        a.record()
+        self._pending.append([a, None])
         return self
 
     def __exit__(self, *exc):
-        self.b.record()
-        self._pending = (self.a, self.b)
+        b = torch.cuda.Event(enable_timing=True)
+        b.record()
+        self._pending[-1][1] = b
         return False
 
     def collect(self):
         torch.cuda.synchronize()
-        self.ms.append(self._pending[0].elapsed_time(self._pending[1]))
+        self.ms.extend(a.elapsed_time(b) for a, b in self._pending)
+        self._pending = []
 
 
 def bench_kcore(spec, steps, warmup):
@@ -127,19 +131,16 @@ def bench_kcore(spec, steps, warmup):
     torch.cuda.synchronize()
     deg0 = csr.deg.cpu().numpy().view(np.uint32).copy()
 
+    # the timed region: K steps between two synchronisations, each call bracketed
+    # by HIP events on the stream it runs on
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        pk.hg_build(e, n, out=csr, ws=ws_b)
-        pk.peel_kcore(e, n, spec.k, csr, max_rounds=max_rounds, out=out, ws=ws_p)
+        step(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-
-    # per-call HIP-event durations, measured in separate passes
-    for _ in range(steps):
-        step(True)
-        tb.collect()
-        tp.collect()
+    tb.collect()
+    tp.collect()
 
     summ = out.summary.cpu().numpy().view(np.uint32)
     vr = out.vertex_round.cpu().numpy().view(np.uint32)

@@ -7,13 +7,16 @@
 // GPU, so the build keeps them out of the per-incidence work.  It is a
 // two-level counting sort:
 //   1. bin count    each workgroup takes a tile of edges and counts, in LDS,
-//                   its incidences per bucket of 16384 consecutive vertices;
+//                   its incidences per bucket of 8192 consecutive vertices;
 //   2. scan         exclusive scan of the bucket-major (bucket, tile) counts;
 //   3. bin scatter  each tile writes its (vertex, edge) pairs into its slice of
 //                   every bucket (LDS cursors, coalesced runs);
 //   4. bucket build one workgroup per bucket counts degrees in LDS, scans them
-//                   into offsets and places the edge ids with LDS cursors.
-// Above 4096 buckets (n > 2^26) the LDS histograms do not fit and the build
+//                   into offsets, places the edge ids with LDS cursors into an
+//                   LDS copy of the bucket's lists and writes that out in one
+//                   coalesced pass (a bucket too large for LDS is placed
+//                   directly in device memory instead).
+// Above 8192 buckets (n > 2^26) the LDS histograms do not fit and the build
 // falls back to one device atomic per incidence for the degrees and another
 // for the cursors.
 #include "common.hpp"
@@ -24,9 +27,10 @@ namespace {
 
 constexpr int kScanItems = 8;                   // values per thread in the scans
 constexpr int kScanTile = kBlock * kScanItems;  // 2048 values per workgroup
-constexpr int kBinShift = 14;                   // 16384 vertices per bucket
+constexpr int kBinShift = 13;                   // 8192 vertices per bucket
 constexpr int kBinV = 1 << kBinShift;
-constexpr int kMaxBuckets = 4096;
+constexpr int kMaxBuckets = 8192;
+constexpr uint32_t kStageCap = 28672;           // incidences of a bucket staged in LDS
 constexpr uint64_t kTileEdges = 16384;          // edges per bin tile
 constexpr int kBT = 1024;                       // threads per workgroup in the bin kernels
 
@@ -200,6 +204,7 @@ __global__ void __launch_bounds__(kBT)
                 const uint32_t *__restrict__ hist, const uint32_t *total, uint32_t *offsets,
                 uint32_t *inc, uint32_t *deg, uint32_t *pmax) {
   __shared__ uint32_t cnt[kBinV + kBinV / 32];
+  __shared__ uint32_t stage[kStageCap];
   __shared__ uint32_t lds[kBT / kWave + 1];
   const uint32_t b = blockIdx.x;
   const uint32_t base = hist[(uint64_t)b * ntiles];
@@ -238,10 +243,21 @@ __global__ void __launch_bounds__(kBT)
     if (b == nb - 1) offsets[n] = end;
   }
   __syncthreads();
-  for (uint32_t p = base + threadIdx.x; p < end; p += kBT) {
-    const uint64_t pr = pairs[p];
-    const uint32_t pos = atomicAdd(&cnt[pad(static_cast<uint32_t>(pr) - v0)], 1u);
-    inc[base + pos] = static_cast<uint32_t>(pr >> 32);
+  const uint32_t total_b = end - base;
+  if (total_b <= kStageCap) {
+    for (uint32_t p = base + threadIdx.x; p < end; p += kBT) {
+      const uint64_t pr = pairs[p];
+      const uint32_t pos = atomicAdd(&cnt[pad(static_cast<uint32_t>(pr) - v0)], 1u);
+      stage[pos] = static_cast<uint32_t>(pr >> 32);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < total_b; i += kBT) inc[base + i] = stage[i];
+  } else {
+    for (uint32_t p = base + threadIdx.x; p < end; p += kBT) {
+      const uint64_t pr = pairs[p];
+      const uint32_t pos = atomicAdd(&cnt[pad(static_cast<uint32_t>(pr) - v0)], 1u);
+      inc[base + pos] = static_cast<uint32_t>(pr >> 32);
+    }
   }
 }
 

@@ -60,7 +60,7 @@ constexpr int kOT = 1024;             // threads per owner workgroup
 constexpr uint32_t kOwnMaxV = 98304;  // owned vertices (LDS degree bytes)
 constexpr uint32_t kOwnMaxE = 131072; // owned edges (LDS alive bits)
 constexpr uint32_t kOwnMaxT = 1024;   // owner workgroups (LDS per-destination counters)
-constexpr uint64_t kDenseRatio = 32;  // dense round when |F_{t-1}| * 32 >= alive edges
+constexpr uint64_t kDenseRatio = 3;   // dense round when |F_{t-1}| * 3 >= alive edges
 constexpr uint32_t kNoVertex = 0xffffffffu;
 
 enum : uint32_t { kModeUndecided = 0, kModeOwnerDone = 1, kModeGlobal = 2 };
@@ -105,7 +105,7 @@ struct PeelArgs {
   uint32_t k;
   uint32_t max_rounds;
   uint32_t force_global;  // PEEL_ENGINE=global: skip the owner engine (testing)
-  uint32_t round_policy;  // PEEL_ROUNDS=dense|sparse: one kind of owner round only (testing)
+  uint32_t round_policy;  // PEEL_ROUNDS=sparse (default) | dense | auto (chosen per round)
 };
 
 __global__ void k_peel_init(PeelCtrl *ctrl) {
@@ -118,7 +118,11 @@ __global__ void k_peel_init(PeelCtrl *ctrl) {
 
 template <int R>
 __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
-  __shared__ uint32_t deg8[kOwnMaxV / 4];  // 4 degree bytes per word
+  // One byte per owned vertex: its degree while alive (255 = held in the global
+  // degree array instead), its removal round once removed (255 = t >= 255,
+  // written to vertex_round directly).  `gone` marks the removed vertices.
+  __shared__ uint32_t deg8[kOwnMaxV / 4];
+  __shared__ uint32_t gone[kOwnMaxV / 32];
   __shared__ uint32_t alive[kOwnMaxE / 32];
   __shared__ uint32_t cnt[kOwnMaxT];
   __shared__ uint32_t cur[kOwnMaxT];
@@ -149,7 +153,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   uint32_t *myF = a.fa + v0;
   uint32_t *myStage = a.stage + (uint64_t)slot * Eb * R;
   const uint32_t *myClaims = a.qclaim + (uint64_t)slot * Eb * R;
-  const uint32_t *myDecs = a.qdec + a.offsets[v0];
+  uint32_t *myDecs = a.qdec + a.offsets[v0];
 
   // ---- init: LDS degrees, alive bits, outputs, F_1 --------------------------
   if (tid == 0) s_n = 0;
@@ -162,12 +166,12 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       if (v < v1) {
         const uint32_t d = a.deg[v];
         word |= (d >= 255u ? 255u : d) << (8 * i);
-        a.vr[v] = 0;
         if (d < k) myF[atomicAdd(&s_n, 1u)] = v;
       }
     }
     deg8[w] = word;
   }
+  for (uint32_t w = tid; w < Vb / 32; w += kOT) gone[w] = 0;
   for (uint32_t w = tid; w < (Eb + 31) / 32; w += kOT) {
     const uint64_t lo = e0 + 32ull * w;
     uint32_t bits = 0;
@@ -180,6 +184,20 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   __syncthreads();
   uint32_t fcnt = s_n;
 
+  // v leaves in round t with every edge it still holds, so its final degree
+  // is 0; its byte now keeps the round (vertex_round is written at the end)
+  auto mark_removed = [&](uint32_t v, uint32_t lv, uint32_t t) {
+    const uint32_t sh = 8 * (lv & 3);
+    atomicOr(&gone[lv >> 5], 1u << (lv & 31));
+    atomicAnd(&deg8[lv >> 2], ~(255u << sh));
+    if (t < 255u)
+      atomicOr(&deg8[lv >> 2], t << sh);
+    else {
+      atomicOr(&deg8[lv >> 2], 255u << sh);
+      a.vr[v] = t;
+    }
+  };
+
   uint32_t epoch = 0;
   uint64_t removed = 0;
   uint64_t alive_m = m;  // edges alive at the start of the round
@@ -187,13 +205,17 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   uint32_t t = 1;
   for (;; ++t) {
     const bool over = t > a.max_rounds;
-    // Two ways to find the edges that die in round t.  Dense: every edge owner
-    // streams the rows of its alive edges and tests their slots against F_t,
-    // published as a bitmap (n bits, which stays in L2).  Sparse: every vertex
-    // of F_t sends a claim for each incident edge to the edge's owner (random
-    // reads of the CSR, about 512 bytes per frontier vertex against 16 bytes
-    // per alive edge for the scan).  Every workgroup takes the same decision
-    // from the same global counts.
+    // Two ways to find the edges that die in round t.  Sparse (the default):
+    // every vertex of F_t that still holds an edge sends a claim for each
+    // incident edge to the edge's owner.  Dense: every edge owner streams the
+    // rows of its alive edges and tests their slots against F_t, published as
+    // a bitmap (n bits, which stays in L2).  Both are bound by random reads: a
+    // few CSR lines per frontier vertex against R bitmap tests per alive edge.
+    // Measured on the n = 2^24 workloads, sparse rounds are never slower by
+    // much and the scan loses badly above the threshold, so dense rounds run
+    // only when asked for (every round, or chosen per round by the size of the
+    // last frontier against the alive edges).  Every workgroup takes the same
+    // decision from the same global counts.
     const bool dense = a.round_policy == kRoundsAuto ? (t == 1 || prev_v * kDenseRatio >= alive_m)
                                                       : a.round_policy == kRoundsDense;
     if (!over && dense) {
@@ -204,13 +226,8 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       for (uint32_t i = tid; i < fcnt; i += kOT) {
         const uint32_t v = myF[i];
         const uint32_t lv = v - v0;
-        a.vr[v] = t;
         atomicOr(&fbl[lv >> 5], 1u << (lv & 31));
-        const uint32_t sh = 8 * (lv & 3);
-        if (((deg8[lv >> 2] >> sh) & 255u) == 255u)
-          a.deg[v] = 0;
-        else
-          atomicAnd(&deg8[lv >> 2], ~(255u << sh));
+        mark_removed(v, lv, t);
       }
       __syncthreads();
       for (uint32_t w = tid; w < (v1 - v0 + 31) / 32; w += kOT) a.fbits[v0 / 32 + w] = fbl[w];
@@ -219,50 +236,54 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     // holds an edge.  The incidence lists of up to kOT frontier vertices at a
     // time are laid end to end (workgroup scan of their lengths) and walked one
     // incidence per thread, so every thread's loads are independent of the
-    // list lengths.
+    // list lengths.  The claims are counted per destination and kept in order
+    // in this workgroup's decrement queue, which is idle until the edge owners
+    // write it after the next barrier and is as long as my vertices' lists;
+    // then they are copied to their destinations.  The CSR is read once.
     if (!over && !dense) {
+      uint32_t *claims = myDecs;
       for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
       __syncthreads();
-      for (int pass = 0; pass < 2; ++pass) {
-        for (uint32_t c0 = 0; c0 < fcnt; c0 += kOT) {
-          uint32_t st = 0, len = 0;
-          if (c0 + tid < fcnt) {
-            const uint32_t v = myF[c0 + tid];
-            const uint32_t lv = v - v0;
-            const uint32_t d8 = (deg8[lv >> 2] >> (8 * (lv & 3))) & 255u;
-            if (pass == 0) a.vr[v] = t;
-            if (d8 != 0) {  // a vertex of degree 0 holds no alive edge
-              st = a.offsets[v];
-              len = a.offsets[v + 1] - st;
-            }
+      uint32_t nc = 0;  // claims so far (same in every thread)
+      for (uint32_t c0 = 0; c0 < fcnt; c0 += kOT) {
+        uint32_t st = 0, len = 0;
+        if (c0 + tid < fcnt) {
+          const uint32_t v = myF[c0 + tid];
+          const uint32_t lv = v - v0;
+          const uint32_t d8 = (deg8[lv >> 2] >> (8 * (lv & 3))) & 255u;
+          mark_removed(v, lv, t);
+          if (d8 != 0) {  // a vertex of degree 0 holds no alive edge
+            st = a.offsets[v];
+            len = a.offsets[v + 1] - st;
           }
-          uint32_t tot;
-          const uint32_t ex = block_exclusive_scan<kOT>(len, &tot, scan_lds);
-          s_start[tid] = st;
-          s_pre[tid] = ex;
-          __syncthreads();
-          for (uint32_t j = tid; j < tot; j += kOT) {
-            // the last list whose start is <= j holds incidence j
-            uint32_t lo = 0, hi = kOT;
-            while (hi - lo > 1) {
-              const uint32_t mid = (lo + hi) >> 1;
-              if (s_pre[mid] <= j) lo = mid; else hi = mid;
-            }
-            const uint32_t e = a.inc[s_start[lo] + (j - s_pre[lo])];
-            if (pass == 0)
-              atomicAdd(&cnt[e / Eb], 1u);
-            else
-              a.qclaim[atomicAdd(&cur[e / Eb], 1u)] = e;
-          }
-          __syncthreads();
         }
-        if (pass == 0) {
-          for (uint32_t d = tid; d < T; d += kOT) {
-            const uint32_t c = cnt[d];
-            cur[d] = c ? d * Eb * R + atomicAdd(&ctrl->qh_claim[d], c) : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<kOT>(len, &tot, scan_lds);
+        s_start[tid] = st;
+        s_pre[tid] = ex;
+        __syncthreads();
+        for (uint32_t j = tid; j < tot; j += kOT) {
+          // the last list whose start is <= j holds incidence j
+          uint32_t lo = 0, hi = kOT;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= j) lo = mid; else hi = mid;
           }
-          __syncthreads();
+          const uint32_t e = a.inc[s_start[lo] + (j - s_pre[lo])];
+          claims[nc + j] = e;
+          atomicAdd(&cnt[e / Eb], 1u);
         }
+        nc += tot;
+        __syncthreads();
+      }
+      for (uint32_t d = tid; d < T; d += kOT) {
+        const uint32_t c = cnt[d];
+        cur[d] = c ? d * Eb * R + atomicAdd(&ctrl->qh_claim[d], c) : 0u;
+      }
+      __syncthreads();
+      for (uint32_t i = tid; i < nc; i += kOT) {
+        const uint32_t e = claims[i];
+        a.qclaim[atomicAdd(&cur[e / Eb], 1u)] = e;
       }
     }
     uint64_t vt;
@@ -378,6 +399,8 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     for (uint32_t i = tid; i < ndec; i += kOT) {
       const uint32_t u = myDecs[i];
       const uint32_t lv = u - v0;
+      // a vertex removed this round (its edges die with it) keeps its round
+      if ((gone[lv >> 5] >> (lv & 31)) & 1u) continue;
       const uint32_t sh = 8 * (lv & 3);
       uint32_t old;
       if (((deg8[lv >> 2] >> sh) & 255u) == 255u)
@@ -390,11 +413,17 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     fcnt = s_n;
   }
 
-  // ---- epilogue: final degrees of the vertices kept in LDS --------------------
+  // ---- epilogue: removal rounds and final degrees, written in order ----------
   for (uint32_t v = v0 + tid; v < v1; v += kOT) {
     const uint32_t lv = v - v0;
-    const uint32_t d = (deg8[lv >> 2] >> (8 * (lv & 3))) & 255u;
-    if (d != 255u) a.deg[v] = d;
+    const uint32_t b = (deg8[lv >> 2] >> (8 * (lv & 3))) & 255u;
+    if ((gone[lv >> 5] >> (lv & 31)) & 1u) {
+      a.deg[v] = 0;
+      if (b != 255u) a.vr[v] = b;
+    } else {
+      a.vr[v] = 0;
+      if (b != 255u) a.deg[v] = b;
+    }
   }
   if (slot == 0 && tid == 0) {
     ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
@@ -639,10 +668,10 @@ extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r,
   const char *engine = std::getenv("PEEL_ENGINE");
   a.force_global = (engine && std::strcmp(engine, "global") == 0) ? 1u : 0u;
   const char *rounds = std::getenv("PEEL_ROUNDS");
-  a.round_policy = !rounds ? kRoundsAuto
-                   : std::strcmp(rounds, "dense") == 0  ? kRoundsDense
-                   : std::strcmp(rounds, "sparse") == 0 ? kRoundsSparse
-                                                         : kRoundsAuto;
+  a.round_policy = !rounds ? kRoundsSparse
+                   : std::strcmp(rounds, "dense") == 0 ? kRoundsDense
+                   : std::strcmp(rounds, "auto") == 0  ? kRoundsAuto
+                                                        : kRoundsSparse;
 
   hipLaunchKernelGGL(k_peel_init, dim3(1), dim3(256), 0, s, a.ctrl);
   PEEL_HIP_TRY(hipGetLastError());

@@ -45,11 +45,11 @@ def _check_against_oracle(n, edges, k, res, max_rounds=1 << 20):
     return o
 
 
-@pytest.fixture(params=["auto", "dense", "sparse"])
+@pytest.fixture(params=["default", "dense", "auto"])
 def rounds(request, monkeypatch):
-    """Which rounds the owner engine runs: chosen per round (auto), or all dense
-    (edge scan against the frontier bitmap), or all sparse (claims over the CSR)."""
-    if request.param == "auto":
+    """Which rounds the owner engine runs: the default (all sparse: claims over the
+    CSR), all dense (edge scan against the frontier bitmap), or chosen per round."""
+    if request.param == "default":
         monkeypatch.delenv("PEEL_ROUNDS", raising=False)
     else:
         monkeypatch.setenv("PEEL_ROUNDS", request.param)
@@ -83,6 +83,8 @@ def test_degenerate_inputs(rounds):
         (7, 2, np.array([[0, 1, 2], [0, 3, 4], [0, 5, 6]], np.uint32)),  # star
         (2, 2, np.array([[0, 0], [1, 1], [0, 1]], np.uint32)),     # repeated ids in an edge
         (8, 2, np.array([[j] * 8 for j in range(8)], np.uint32)),  # r = 8, loops
+        # one CSR bucket with more incidences than the build stages in LDS
+        (100, 3, np.random.default_rng(3).integers(0, 100, size=(12000, 4)).astype(np.uint32)),
     ]
     for n, k, e in cases:
         say("degenerate", rounds, n, k, e.shape)
@@ -159,7 +161,7 @@ def test_full_size_sweep_r4_n16M(c):
     need_gpu()
     spec = configs.kcore_sweep(c)
     e = spec.edges(1)
-    say(spec.name, "rounds", os.environ.get("PEEL_ROUNDS", "auto"))
+    say(spec.name, "rounds", os.environ.get("PEEL_ROUNDS", "default"))
     res = gpu_peel(spec.n, e, spec.k)
     assert res["flags"] == 0
     _check_against_oracle(spec.n, e, spec.k, res)
@@ -169,7 +171,7 @@ def test_full_size_sweep_r4_n16M(c):
                                         res["edge_rounds"]) == []
 
 
-@pytest.mark.parametrize("c,mode", [(0.70, "sparse"), (0.85, "dense")])
+@pytest.mark.parametrize("c,mode", [(0.70, "dense"), (0.85, "auto")])
 def test_full_size_forced_round_kind(c, mode, monkeypatch):
     # every round of one kind at full size: both kinds give the oracle's answer
     need_gpu()
