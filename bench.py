@@ -286,7 +286,8 @@ def bench_serve(spec, n_cal, n_rate, warm):
     fifo = FifoServer(spec.budget_bytes, fill)
     fifo_sat = latency_stats(fifo.run(reqs(n_cal, 0.0, 5)))["req_per_s"]
     out = {"workload": spec.name, "budget_gb": spec.budget_bytes / 2 ** 30,
-           "small_cells": cont.small_cells, "saturated_req_per_s": lam,
+           "small_cells": cont.small_cells, "large_lanes": len(cont.large_streams),
+           "saturated_req_per_s": lam,
            "fifo_saturated_req_per_s": fifo_sat, "warmup_requests": warm, "rates": []}
     for i, frac in enumerate((0.3, 0.6, 0.9)):
         rate = frac * lam

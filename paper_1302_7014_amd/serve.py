@@ -9,13 +9,14 @@ first served as arena space frees up, and runs the GPU as a pipeline:
   with ``iblt_insert`` on the insert stream (this stands for receiving the
   table), overlapping whatever listing is running;
 * listing, routed by table size: a table of more than ``small_cells`` cells is
-  listed alone by ``iblt_list`` (every CU that is free takes part) on the large
-  lane's stream, as soon as its insert is done; the small tables that are
+  listed alone by ``iblt_list`` on one of ``large_lanes`` streams (taken in
+  turn), as soon as its insert is done.  Each such run forms its team from the
+  CUs that are free, and a run on a mid-sized table is bound by its per-round
+  barriers, so runs on several lanes overlap well.  The small tables that are
   inserted and not yet listed are listed together in one
   ``iblt_list_batched`` launch (one workgroup per table) on a small-lane
   stream, up to ``max_inflight`` such launches at once.  One workgroup lists a
-  small table about as fast as the whole chip does (the chip's run is bound by
-  its per-round barriers), so small tables cost the large lane nothing;
+  small table about as fast as the whole chip does;
 * retirement: when a launch's completion event fires, its requests complete,
   their arena space is freed and their results (the summary) are kept.
 
@@ -167,7 +168,8 @@ class ContinuousServer(_Base):
 
     def __init__(self, budget: int, fill_keys, max_cells: int, max_rounds: int = 256,
                  max_inflight: int = 2, block_threads: int = 512, small_cells: int = 1 << 12,
-                 keep_keys: bool = False, device="cuda"):
+                 large_lanes: int = 4, admit_group: int = 8, keep_keys: bool = False,
+                 device="cuda"):
         super().__init__(budget, fill_keys, max_rounds, keep_keys, device)
         self.max_cells = max_cells
         self.max_inflight = max_inflight
@@ -175,23 +177,25 @@ class ContinuousServer(_Base):
         self.small_cells = small_cells
         self.insert_stream = torch.cuda.Stream(device=self.device)
         self.list_streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
-        self.large_stream = torch.cuda.Stream(device=self.device)
+        self.admit_group = admit_group
+        # each large lane: a stream and a listing workspace for the largest table
+        self.large_streams = [torch.cuda.Stream(device=self.device) for _ in range(large_lanes)]
+        self.large_ws = [pk.workspace(pk.iblt_list_workspace(pk.iblt_desc(max_cells, 3, 0)),
+                                      self.device) for _ in range(large_lanes)]
         # one batched-listing workspace per in-flight launch, sized for the largest small table
         self.ws = [pk.workspace(pk.iblt_list_batched_workspace(1 << 16, min(small_cells, max_cells)),
                                 self.device) for _ in range(max_inflight)]
-        self.large_ws = pk.workspace(pk.iblt_list_workspace(pk.iblt_desc(max_cells, 3, 0)),
-                                     self.device)
         self.batches = 0
         self.large = 0
 
-    def _list_large(self, q: Request) -> torch.cuda.Event:
-        s = self.large_stream
+    def _list_large(self, q: Request, lane: int) -> torch.cuda.Event:
+        s = self.large_streams[lane]
         s.wait_event(q._event)
         t = q._table
         with torch.cuda.stream(s):
             pk.iblt_list(t.desc, t.cells, max_rounds=self.max_rounds,
-                         out=pk.ListOut(t.keys, t.round_stats, t.summary), ws=self.large_ws,
-                         stream=s)
+                         out=pk.ListOut(t.keys, t.round_stats, t.summary),
+                         ws=self.large_ws[lane], stream=s)
         ev = torch.cuda.Event()
         ev.record(s)
         self.large += 1
@@ -202,7 +206,8 @@ class ContinuousServer(_Base):
         waiting: list[Request] = []      # arrived, not admitted
         ready: list[Request] = []        # small tables inserted, not listed
         inflight: list[tuple] = []       # (event, requests, slot, entries) of batched launches
-        large: list[tuple] = []          # (event, request) in launch order on the large lane
+        lanes = [[] for _ in self.large_streams]  # per large lane: (event, request) in order
+        next_lane = 0
         free_slots = list(range(self.max_inflight))
         done: list[Request] = []
         t0 = time.perf_counter()
@@ -212,9 +217,10 @@ class ContinuousServer(_Base):
             while i < len(pending) and pending[i].arrival <= now:
                 waiting.append(pending[i])
                 i += 1
-            # admit in arrival order while the arena has room
+            # admit in arrival order while the arena has room, a few at a time so
+            # that listing starts while later arrivals are still being admitted
             admitted = []
-            while waiting:
+            while waiting and len(admitted) < self.admit_group:
                 q = waiting[0]
                 if q.footprint(self.max_rounds) > self.arena.budget:
                     self.rejected.append(waiting.pop(0))
@@ -229,14 +235,16 @@ class ContinuousServer(_Base):
                 for q in admitted:
                     q._event = ev
                     if q.ncells > self.small_cells:
-                        large.append((self._list_large(q), q))
+                        lanes[next_lane].append((self._list_large(q, next_lane), q))
+                        next_lane = (next_lane + 1) % len(lanes)
                     else:
                         ready.append(q)
-            # retire finished work: the large lane completes in launch order
-            while large and large[0][0].query():
-                q = large.pop(0)[1]
-                self._retire(q, time.perf_counter() - t0)
-                done.append(q)
+            # retire finished work: each large lane completes in launch order
+            for lane in lanes:
+                while lane and lane[0][0].query():
+                    q = lane.pop(0)[1]
+                    self._retire(q, time.perf_counter() - t0)
+                    done.append(q)
             still = []
             for ev, qs, slot, ent in inflight:
                 if ev.query():
@@ -265,9 +273,11 @@ class ContinuousServer(_Base):
                 ev.record(s)
                 inflight.append((ev, qs, slot, ent))
                 self.batches += 1
-            if i >= len(pending) and not waiting and not ready and not inflight and not large:
+            if (i >= len(pending) and not waiting and not ready and not inflight
+                    and not any(lanes)):
                 break
-            time.sleep(poll_s)
+            if not waiting:
+                time.sleep(poll_s)
         return done
 
 
