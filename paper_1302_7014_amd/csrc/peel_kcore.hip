@@ -58,7 +58,7 @@ constexpr int kDenseTile = kBlock * kDenseItems;
 
 constexpr int kOT = 1024;             // threads per owner workgroup
 constexpr uint32_t kOwnMaxV = 98304;  // owned vertices (LDS degree bytes)
-constexpr uint32_t kOwnMaxE = 131072; // owned edges (LDS alive bits)
+constexpr uint32_t kOwnMaxE = 65536;  // owned edges (LDS alive and claimed bits)
 constexpr uint32_t kOwnMaxT = 1024;   // owner workgroups (LDS per-destination counters)
 constexpr uint64_t kDenseRatio = 3;   // dense round when |F_{t-1}| * 3 >= alive edges
 constexpr uint32_t kNoVertex = 0xffffffffu;
@@ -116,6 +116,20 @@ __global__ void k_peel_init(PeelCtrl *ctrl) {
 // ===========================================================================
 // Owner engine.
 
+// Position of the r-th set bit (from 0) of x; x has more than r set bits.
+__device__ inline uint32_t nth_set_bit(uint32_t x, uint32_t r) {
+  uint32_t pos = 0, c;
+  c = __popc(x & 0xffffu);
+  if (r >= c) { r -= c; x >>= 16; pos += 16; }
+  c = __popc(x & 0xffu);
+  if (r >= c) { r -= c; x >>= 8; pos += 8; }
+  c = __popc(x & 0xfu);
+  if (r >= c) { r -= c; x >>= 4; pos += 4; }
+  c = __popc(x & 0x3u);
+  if (r >= c) { r -= c; x >>= 2; pos += 2; }
+  return pos + (r >= (x & 1u) ? 1u : 0u);
+}
+
 template <int R>
 __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   // One byte per owned vertex: its degree while alive (255 = held in the global
@@ -124,12 +138,13 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   __shared__ uint32_t deg8[kOwnMaxV / 4];
   __shared__ uint32_t gone[kOwnMaxV / 32];
   __shared__ uint32_t alive[kOwnMaxE / 32];
+  __shared__ uint32_t claimed[kOwnMaxE / 32];  // edges claimed this round
   __shared__ uint32_t cnt[kOwnMaxT];
   __shared__ uint32_t cur[kOwnMaxT];
   __shared__ uint32_t s_start[kOT];
   __shared__ uint32_t s_pre[kOT];
   __shared__ uint32_t scan_lds[kOT / kWave + 1];
-  __shared__ uint32_t fbl[kOwnMaxV / 32];  // dense rounds: this workgroup's slice of F_t
+  __shared__ uint32_t fbl[kOwnMaxV / 32];  // the next frontier, as bits over my vertices
   __shared__ uint32_t s_n, s_w;
 
   PeelCtrl *ctrl = a.ctrl;
@@ -156,33 +171,38 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   uint32_t *myDecs = a.qdec + a.offsets[v0];
 
   // ---- init: LDS degrees, alive bits, outputs, F_1 --------------------------
-  if (tid == 0) s_n = 0;
+  for (uint32_t w = tid; w < Vb / 32; w += kOT) {
+    gone[w] = 0;
+    fbl[w] = 0;
+  }
+  for (uint32_t w = tid; w < (Eb + 31) / 32; w += kOT) {
+    const uint64_t lo = e0 + 32ull * w;
+    uint32_t bits = 0;
+    if (lo < e1) bits = (e1 - lo >= 32) ? 0xffffffffu : ((1u << (uint32_t)(e1 - lo)) - 1u);
+    alive[w] = bits;
+    claimed[w] = 0;
+  }
   __syncthreads();
   for (uint32_t w = tid; w < (Vb + 3) / 4; w += kOT) {
-    uint32_t word = 0;
+    uint32_t word = 0, low = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t v = v0 + 4 * w + i;
       if (v < v1) {
         const uint32_t d = a.deg[v];
         word |= (d >= 255u ? 255u : d) << (8 * i);
-        if (d < k) myF[atomicAdd(&s_n, 1u)] = v;
+        if (d < k) low |= 1u << i;
       }
     }
     deg8[w] = word;
-  }
-  for (uint32_t w = tid; w < Vb / 32; w += kOT) gone[w] = 0;
-  for (uint32_t w = tid; w < (Eb + 31) / 32; w += kOT) {
-    const uint64_t lo = e0 + 32ull * w;
-    uint32_t bits = 0;
-    if (lo < e1) bits = (e1 - lo >= 32) ? 0xffffffffu : ((1u << (uint32_t)(e1 - lo)) - 1u);
-    alive[w] = bits;
+    if (low) atomicOr(&fbl[w >> 3], low << (4 * (w & 7)));
   }
   for (uint64_t e = e0 + tid; e < e1; e += kOT) a.er[e] = 0;
   if (slot == 0)
     for (uint64_t i = tid; i < 2ull * a.max_rounds; i += kOT) a.stats[i] = 0;
+  if (tid == 0) s_n = ~0u;  // F_1 is taken from the bitmap
   __syncthreads();
-  uint32_t fcnt = s_n;
+  uint32_t fcnt = 0;
 
   // v leaves in round t with every edge it still holds, so its final degree
   // is 0; its byte now keeps the round (vertex_round is written at the end)
@@ -218,19 +238,49 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     // decision from the same global counts.
     const bool dense = a.round_policy == kRoundsAuto ? (t == 1 || prev_v * kDenseRatio >= alive_m)
                                                       : a.round_policy == kRoundsDense;
-    if (!over && dense) {
-      // ---- dense: publish F_t; its vertices leave with every edge they hold,
-      // so their degrees go to 0 now and the edge scan sends them no decrement
-      for (uint32_t w = tid; w < Vb / 32; w += kOT) fbl[w] = 0;
-      __syncthreads();
+    // ---- F_t in vertex order: the bitmap is compacted into myF (and cleared for
+    // F_{t+1}); a dense round also publishes it.  Walking F_t in vertex order
+    // makes neighbouring frontier vertices share the lines of the CSR.
+    // A frontier of at most kOT vertices was also listed in s_start by the
+    // decrement phase: it is taken from there (its bits cleared one by one)
+    // instead of scanning the whole bitmap.
+    const bool publish = dense && !over;
+    if (s_n <= (uint32_t)kOT && !publish) {
+      fcnt = s_n;
       for (uint32_t i = tid; i < fcnt; i += kOT) {
-        const uint32_t v = myF[i];
-        const uint32_t lv = v - v0;
-        atomicOr(&fbl[lv >> 5], 1u << (lv & 31));
-        mark_removed(v, lv, t);
+        const uint32_t v = s_start[i];
+        myF[i] = v;
+        atomicAnd(&fbl[(v - v0) >> 5], ~(1u << ((v - v0) & 31)));
       }
       __syncthreads();
-      for (uint32_t w = tid; w < (v1 - v0 + 31) / 32; w += kOT) a.fbits[v0 / 32 + w] = fbl[w];
+    } else {
+      const uint32_t nw = (v1 - v0 + 31) / 32;
+      fcnt = 0;
+      for (uint32_t w0 = 0; w0 < nw; w0 += kOT) {
+        const uint32_t w = w0 + tid;
+        uint32_t bits = 0;
+        if (w < nw) {
+          bits = fbl[w];
+          fbl[w] = 0;
+          if (publish) a.fbits[v0 / 32 + w] = bits;
+        }
+        uint32_t tot;
+        uint32_t pos = fcnt + block_exclusive_scan<kOT>(__popc(bits), &tot, scan_lds);
+        while (bits) {
+          myF[pos++] = v0 + 32 * w + (__ffs(bits) - 1);
+          bits &= bits - 1;
+        }
+        fcnt += tot;
+      }
+      __syncthreads();
+    }
+    if (!over && dense) {
+      // ---- dense: F_t's vertices leave with every edge they hold, so their
+      // degrees go to 0 now and the edge scan sends them no decrement
+      for (uint32_t i = tid; i < fcnt; i += kOT) {
+        const uint32_t v = myF[i];
+        mark_removed(v, v - v0, t);
+      }
     }
     // ---- sparse: one claim per incidence of every vertex of F_t that still
     // holds an edge.  The incidence lists of up to kOT frontier vertices at a
@@ -351,27 +401,82 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         }
       }
     }
-    const uint32_t nclaims = s_n;
-    for (uint32_t i = tid; i < nclaims; i += kOT) {
-      const uint32_t e = myClaims[i];
-      const uint32_t le = e - (uint32_t)e0;
-      const uint32_t bit = 1u << (le & 31);
-      if (atomicAnd(&alive[le >> 5], ~bit) & bit) {
-        a.er[e] = t;
-        const uint32_t w = atomicAdd(&s_w, 1u);
-        const uint32_t *row = a.edges + (uint64_t)e * R;
-        uint32_t ids[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) ids[j] = row[j];
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-          myStage[(uint64_t)w * R + j] = ids[j];
-          if (ids[j] < n) atomicAdd(&cnt[ids[j] / Vb], 1u);
+    uint32_t won = 0;
+    if (!dense) {
+      // Sparse: mark the claimed edges, then take the claimed edges that are
+      // still alive in edge order (so rows are read and rounds written in
+      // order), one per thread, each placed at its rank in the stage.
+      const uint32_t nclaims = s_n;
+      if (nclaims <= (uint32_t)kOT) {
+        // few claims: one per thread, in arrival order
+        uint32_t e = 0;
+        bool win = false;
+        if (tid < nclaims) {
+          e = myClaims[tid];
+          const uint32_t le = e - (uint32_t)e0;
+          const uint32_t bit = 1u << (le & 31);
+          win = (atomicAnd(&alive[le >> 5], ~bit) & bit) != 0;
         }
+        const uint32_t w = wave_append(win, &s_w);
+        if (win) {
+          a.er[e] = t;
+          const uint32_t *row = a.edges + (uint64_t)e * R;
+          uint32_t ids[R];
+#pragma unroll
+          for (int q = 0; q < R; ++q) ids[q] = row[q];
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            myStage[(uint64_t)w * R + q] = ids[q];
+            if (ids[q] < n) atomicAdd(&cnt[ids[q] / Vb], 1u);
+          }
+        }
+        __syncthreads();
+        won = s_w;
       }
+      for (uint32_t i = tid; nclaims > (uint32_t)kOT && i < nclaims; i += kOT) {
+        const uint32_t le = myClaims[i] - (uint32_t)e0;
+        atomicOr(&claimed[le >> 5], 1u << (le & 31));
+      }
+      __syncthreads();
+      const uint32_t nw = nclaims > (uint32_t)kOT ? (uint32_t)((e1 - e0 + 31) / 32) : 0u;
+      for (uint32_t w0 = 0; w0 < nw; w0 += kOT) {
+        const uint32_t w = w0 + tid;
+        uint32_t dying = 0;
+        if (w < nw) {
+          dying = claimed[w] & alive[w];
+          claimed[w] = 0;
+          alive[w] &= ~dying;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<kOT>(__popc(dying), &tot, scan_lds);
+        s_start[tid] = dying;
+        s_pre[tid] = ex;
+        __syncthreads();
+        for (uint32_t j = tid; j < tot; j += kOT) {
+          uint32_t lo = 0, hi = kOT;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= j) lo = mid; else hi = mid;
+          }
+          const uint64_t e = e0 + 32ull * (w0 + lo) + nth_set_bit(s_start[lo], j - s_pre[lo]);
+          a.er[e] = t;
+          const uint32_t *row = a.edges + e * R;
+          uint32_t ids[R];
+#pragma unroll
+          for (int q = 0; q < R; ++q) ids[q] = row[q];
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            myStage[(uint64_t)(won + j) * R + q] = ids[q];
+            if (ids[q] < n) atomicAdd(&cnt[ids[q] / Vb], 1u);
+          }
+        }
+        won += tot;
+        __syncthreads();
+      }
+    } else {
+      __syncthreads();
+      won = s_w;
     }
-    __syncthreads();
-    const uint32_t won = s_w;
     for (uint32_t d = tid; d < T; d += kOT) {
       const uint32_t c = cnt[d];
       const uint32_t dv = d * Vb < n ? d * Vb : n;
@@ -407,10 +512,13 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         old = atomicSub(&a.deg[u], 1u);
       else
         old = (atomicSub(&deg8[lv >> 2], 1u << sh) >> sh) & 255u;
-      if (old == k) myF[atomicAdd(&s_n, 1u)] = u;
+      if (old == k) {
+        atomicOr(&fbl[lv >> 5], 1u << (lv & 31));
+        const uint32_t p = atomicAdd(&s_n, 1u);
+        if (p < (uint32_t)kOT) s_start[p] = u;
+      }
     }
     __syncthreads();
-    fcnt = s_n;
   }
 
   // ---- epilogue: removal rounds and final degrees, written in order ----------
