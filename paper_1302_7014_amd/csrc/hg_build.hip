@@ -5,20 +5,27 @@
 //
 // Device-scope atomics run at a fixed rate far below HBM bandwidth on this
 // GPU, so the build keeps them out of the per-incidence work.  It is a
-// two-level counting sort:
+// three-level counting sort that keeps every write stream it opens short
+// enough for L2 to fill whole lines:
 //   1. bin count    each workgroup takes a tile of edges and counts, in LDS,
-//                   its incidences per bucket of 8192 consecutive vertices;
-//   2. scan         exclusive scan of the bucket-major (bucket, tile) counts;
+//                   its incidences per bucket of 8192 vertices (and so per
+//                   super-bucket of 65536);
+//   2. scans        exclusive scans of the (super-bucket, tile) counts and of
+//                   the (bucket, tile) counts, both bucket-major: the second
+//                   gives every (bucket, tile) run its final place;
 //   3. bin scatter  each tile writes its (vertex, edge) pairs into its slice of
-//                   every bucket (LDS cursors, coalesced runs);
-//   4. bucket build one workgroup per bucket counts degrees in LDS, scans them
+//                   every super-bucket (LDS cursors; a few hundred open lines
+//                   per workgroup);
+//   4. split        one workgroup per (super-bucket, group of tiles) moves its
+//                   pairs to their (bucket, tile) runs (LDS cursors);
+//   5. bucket build one workgroup per bucket counts degrees in LDS, scans them
 //                   into offsets, places the edge ids with LDS cursors into an
 //                   LDS copy of the bucket's lists and writes that out in one
 //                   coalesced pass (a bucket too large for LDS is placed
 //                   directly in device memory instead).
-// Above 8192 buckets (n > 2^26) the LDS histograms do not fit and the build
-// falls back to one device atomic per incidence for the degrees and another
-// for the cursors.
+// Above 1024 super-buckets (n > 2^26) the LDS histograms do not fit and the
+// build falls back to one device atomic per incidence for the degrees and
+// another for the cursors.
 #include "common.hpp"
 #include "host.hpp"
 
@@ -29,14 +36,19 @@ constexpr int kScanItems = 8;                   // values per thread in the scan
 constexpr int kScanTile = kBlock * kScanItems;  // 2048 values per workgroup
 constexpr int kBinShift = 13;                   // 8192 vertices per bucket
 constexpr int kBinV = 1 << kBinShift;
-constexpr int kMaxBuckets = 8192;
+constexpr int kSupShift = 16;                   // 65536 vertices per super-bucket
+constexpr int kSubPer = 1 << (kSupShift - kBinShift);  // buckets per super-bucket
+constexpr int kMaxSuper = 1024;
+constexpr int kSplitU = 8;                      // pairs per thread in flight in the split
+constexpr int kSplitTiles = 32;                 // tiles per split workgroup
 constexpr uint32_t kStageCap = 28672;           // incidences of a bucket staged in LDS
 constexpr uint64_t kTileEdges = 16384;          // edges per bin tile
 constexpr int kBT = 1024;                       // threads per workgroup in the bin kernels
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+__device__ inline uint64_t ceil_div_dev(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint64_t scan_tiles(uint64_t count) { return ceil_div(count, kScanTile); }
-inline bool binned(uint32_t n) { return ceil_div(n, kBinV) <= kMaxBuckets; }
+inline bool binned(uint32_t n) { return ceil_div(n, 1u << kSupShift) <= kMaxSuper; }
 
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan of a uint32 array (three passes).
@@ -148,13 +160,14 @@ __global__ void __launch_bounds__(kBlock) k_max_u32(const uint32_t *in, uint64_t
 // counters does not hit the same bank as its neighbours.
 __device__ inline uint32_t pad(uint32_t i) { return i + (i >> 5); }
 
-// hist[b * ntiles + tile] = incidences of this edge tile whose vertex is in bucket b.
+// hist8[b * ntiles + tile] = incidences of this edge tile whose vertex is in bucket b;
+// hist[s * ntiles + tile] = the same per super-bucket s.
 template <int R>
 __global__ void __launch_bounds__(kBT)
     k_bin_count(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nb,
-                uint64_t ntiles, uint32_t *hist, uint32_t *info) {
-  __shared__ uint32_t h[kMaxBuckets];
-  for (uint32_t b = threadIdx.x; b < nb; b += kBT) h[b] = 0;
+                uint32_t nsb, uint64_t ntiles, uint32_t *hist, uint32_t *hist8, uint32_t *info) {
+  __shared__ uint32_t h[kMaxSuper * kSubPer];
+  for (uint32_t b = threadIdx.x; b < nsb * kSubPer; b += kBT) h[b] = 0;
   __syncthreads();
   const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
@@ -172,28 +185,84 @@ __global__ void __launch_bounds__(kBT)
   }
   if (bad) atomicOr(&info[0], PEEL_FLAG_ERANGE);
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb; b += kBT) hist[(uint64_t)b * ntiles + blockIdx.x] = h[b];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBT) hist8[(uint64_t)b * ntiles + blockIdx.x] = h[b];
+  for (uint32_t sb = threadIdx.x; sb < nsb; sb += kBT) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < kSubPer; ++q) c += h[sb * kSubPer + q];
+    hist[(uint64_t)sb * ntiles + blockIdx.x] = c;
+  }
 }
 
-// pairs[...] = (edge << 32 | vertex) grouped by bucket, each tile in its own slice.
+// pairs[...] = (edge << 32 | vertex) grouped by super-bucket, each tile in its own slice.
 template <int R>
 __global__ void __launch_bounds__(kBT)
     k_bin_scatter(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nb,
                   uint64_t ntiles, const uint32_t *__restrict__ hist, uint64_t *pairs) {
-  __shared__ uint32_t cur[kMaxBuckets];
+  __shared__ uint32_t cur[kMaxSuper];
   for (uint32_t b = threadIdx.x; b < nb; b += kBT) cur[b] = hist[(uint64_t)b * ntiles + blockIdx.x];
   __syncthreads();
   const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
-  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBT) {
-    const uint32_t *row = edges + e * R;
+  constexpr int kU = 4;  // rows per thread in flight
+  for (uint64_t eb = e0 + threadIdx.x; eb < e1; eb += kU * kBT) {
+    uint32_t ids[kU][R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const uint32_t v = row[j];
-      if (v < n) {
-        const uint32_t pos = atomicAdd(&cur[v >> kBinShift], 1u);
-        pairs[pos] = (e << 32) | v;
+    for (int u = 0; u < kU; ++u) {
+      const uint64_t e = eb + (uint64_t)u * kBT;
+#pragma unroll
+      for (int j = 0; j < R; ++j) ids[u][j] = e < e1 ? edges[e * R + j] : ~0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint64_t e = eb + (uint64_t)u * kBT;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint32_t v = ids[u][j];
+        if (v < n) {
+          const uint32_t pos = atomicAdd(&cur[v >> kSupShift], 1u);
+          pairs[pos] = (e << 32) | v;
+        }
       }
+    }
+  }
+}
+
+// One workgroup per (super-bucket sb, group of kSplitTiles tiles): the pairs of
+// those tiles in sb's slice of pairs_in go to their (bucket, tile) runs in
+// pairs_out, whose starts are the scanned hist8.  A pair's tile is its edge id's.
+__global__ void __launch_bounds__(kBT)
+    k_bin_split(const uint64_t *__restrict__ pairs_in, uint32_t nb, uint32_t nsb,
+                uint64_t ntiles, const uint32_t *__restrict__ hist, const uint32_t *total,
+                const uint32_t *__restrict__ hist8, uint64_t *pairs_out) {
+  __shared__ uint32_t cur[kSubPer * kSplitTiles];
+  const uint64_t ngroups = ceil_div_dev(ntiles, kSplitTiles);
+  const uint32_t sb = static_cast<uint32_t>(blockIdx.x / ngroups);
+  const uint64_t t0 = (blockIdx.x % ngroups) * kSplitTiles;
+  const uint64_t t1 = t0 + kSplitTiles < ntiles ? t0 + kSplitTiles : ntiles;
+  const uint32_t base = hist[(uint64_t)sb * ntiles + t0];
+  const uint32_t end = t1 < ntiles                 ? hist[(uint64_t)sb * ntiles + t1]
+                       : (sb + 1 < nsb)             ? hist[(uint64_t)(sb + 1) * ntiles]
+                                                    : *total;
+  const uint32_t b0 = sb * kSubPer;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(kSubPer * kSplitTiles); i += kBT) {
+    const uint32_t q = i / kSplitTiles, g = i % kSplitTiles;
+    cur[i] = (b0 + q < nb && t0 + g < t1) ? hist8[(uint64_t)(b0 + q) * ntiles + t0 + g] : 0u;
+  }
+  __syncthreads();
+  for (uint32_t p0 = base; p0 < end; p0 += kSplitU * kBT) {
+    uint64_t pr[kSplitU];
+#pragma unroll
+    for (int u = 0; u < kSplitU; ++u) {
+      const uint32_t p = p0 + u * kBT + threadIdx.x;
+      pr[u] = p < end ? pairs_in[p] : ~0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kSplitU; ++u) {
+      if (pr[u] == ~0ull) continue;
+      const uint32_t q = (static_cast<uint32_t>(pr[u]) >> kBinShift) - b0;
+      const uint32_t g = static_cast<uint32_t>((pr[u] >> 32) / kTileEdges - t0);
+      pairs_out[atomicAdd(&cur[q * kSplitTiles + g], 1u)] = pr[u];
     }
   }
 }
@@ -201,14 +270,14 @@ __global__ void __launch_bounds__(kBT)
 // One workgroup per bucket: degrees, offsets and edge lists of its vertices.
 __global__ void __launch_bounds__(kBT)
     k_bin_build(const uint64_t *__restrict__ pairs, uint32_t n, uint32_t nb, uint64_t ntiles,
-                const uint32_t *__restrict__ hist, const uint32_t *total, uint32_t *offsets,
+                const uint32_t *__restrict__ hist8, const uint32_t *total, uint32_t *offsets,
                 uint32_t *inc, uint32_t *deg, uint32_t *pmax) {
   __shared__ uint32_t cnt[kBinV + kBinV / 32];
   __shared__ uint32_t stage[kStageCap];
   __shared__ uint32_t lds[kBT / kWave + 1];
   const uint32_t b = blockIdx.x;
-  const uint32_t base = hist[(uint64_t)b * ntiles];
-  const uint32_t end = (b + 1 < nb) ? hist[(uint64_t)(b + 1) * ntiles] : *total;
+  const uint32_t base = hist8[(uint64_t)b * ntiles];
+  const uint32_t end = (b + 1 < nb) ? hist8[(uint64_t)(b + 1) * ntiles] : *total;
   const uint32_t v0 = b << kBinShift;
   const uint32_t nv = (n - v0) < (uint32_t)kBinV ? (n - v0) : (uint32_t)kBinV;
   for (uint32_t i = threadIdx.x; i < (uint32_t)(kBinV + kBinV / 32); i += kBT) cnt[i] = 0;
@@ -304,7 +373,7 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---------------------------------------------------------------------------
 struct Sizes {
-  uint64_t ntiles, nb, hist, pairs;
+  uint64_t ntiles, nb, nsb, hist, hist8, pairs;
 };
 
 Sizes sizes(uint32_t n, uint64_t m, uint32_t r) {
@@ -312,7 +381,9 @@ Sizes sizes(uint32_t n, uint64_t m, uint32_t r) {
   if (binned(n)) {
     z.ntiles = ceil_div(m, kTileEdges);
     z.nb = ceil_div(n, kBinV);
-    z.hist = (z.ntiles ? z.ntiles : 1) * z.nb;
+    z.nsb = ceil_div(n, 1u << kSupShift);
+    z.hist = (z.ntiles ? z.ntiles : 1) * z.nsb;
+    z.hist8 = (z.ntiles ? z.ntiles : 1) * z.nb;
     z.pairs = m * r;
   } else {
     z.hist = (uint64_t)n + 1;  // degrees then cursors
@@ -322,9 +393,9 @@ Sizes sizes(uint32_t n, uint64_t m, uint32_t r) {
 
 size_t build_ws_bytes(uint32_t n, uint64_t m, uint32_t r) {
   const Sizes z = sizes(n, m, r);
-  const uint64_t scan_n = z.hist > n ? z.hist : n;
-  return align_up(z.hist * 4) + 2 * align_up(scan_tiles(scan_n) * 4 + 4) +
-         align_up(z.pairs * 8) + align_up((z.nb + 1) * 4) + 256;
+  const uint64_t scan_n = z.hist8 > n ? z.hist8 : n;
+  return align_up(z.hist * 4) + align_up(z.hist8 * 4) + 3 * align_up(scan_tiles(scan_n) * 4 + 4) +
+         2 * align_up((z.pairs ? z.pairs : 1) * 8) + align_up((z.nb + 4) * 4) + 512;
 }
 
 template <int R>
@@ -332,24 +403,32 @@ peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t
                          uint32_t *inc, uint32_t *deg, uint32_t *info, Carver &c, hipStream_t s) {
   const Sizes z = sizes(n, m, R);
   uint32_t *hist = c.take<uint32_t>(z.hist);
+  uint32_t *hist8 = c.take<uint32_t>(z.hist8);
   uint32_t *part = c.take<uint32_t>(scan_tiles(z.hist) + 1);
+  uint32_t *part8 = c.take<uint32_t>(scan_tiles(z.hist8) + 1);
   uint64_t *pairs = c.take<uint64_t>(z.pairs ? z.pairs : 1);
-  uint32_t *pmax = c.take<uint32_t>(z.nb + 1);
-  uint32_t *total = pmax + z.nb;
+  uint64_t *pairs2 = c.take<uint64_t>(z.pairs ? z.pairs : 1);
+  uint32_t *pmax = c.take<uint32_t>(z.nb + 4);
+  uint32_t *total = pmax + z.nb;      // pairs, from the super-bucket scan
+  uint32_t *total8 = pmax + z.nb + 1; // the same, from the bucket scan
   if (z.ntiles) {
     hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
-                       (uint32_t)z.nb, z.ntiles, hist, info);
+                       (uint32_t)z.nb, (uint32_t)z.nsb, z.ntiles, hist, hist8, info);
     scan_u32(hist, z.hist, hist, nullptr, part, nullptr, total, nullptr, s);
+    scan_u32(hist8, z.hist8, hist8, nullptr, part8, nullptr, total8, nullptr, s);
     hipLaunchKernelGGL(k_bin_scatter<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
-                       (uint32_t)z.nb, z.ntiles, hist, pairs);
+                       (uint32_t)z.nsb, z.ntiles, hist, pairs);
+    const uint64_t groups = ceil_div(z.ntiles, kSplitTiles);
+    hipLaunchKernelGGL(k_bin_split, dim3(z.nsb * groups), dim3(kBT), 0, s, pairs,
+                       (uint32_t)z.nb, (uint32_t)z.nsb, z.ntiles, hist, total, hist8, pairs2);
   } else {
     // no edges: every bucket is empty
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(z.nb, kBlock, 4096)), dim3(kBlock), 0, s,
-                       hist, z.nb, 0u);
-    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(kBlock), 0, s, total, (uint64_t)1, 0u);
+                       hist8, z.nb, 0u);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(kBlock), 0, s, total8, (uint64_t)1, 0u);
   }
-  hipLaunchKernelGGL(k_bin_build, dim3(z.nb), dim3(kBT), 0, s, pairs, n, (uint32_t)z.nb,
-                     z.ntiles ? z.ntiles : 1, hist, total, offsets, inc, deg, pmax);
+  hipLaunchKernelGGL(k_bin_build, dim3(z.nb), dim3(kBT), 0, s, pairs2, n, (uint32_t)z.nb,
+                     z.ntiles ? z.ntiles : 1, hist8, total8, offsets, inc, deg, pmax);
   hipLaunchKernelGGL(k_max_u32, dim3(1), dim3(kBlock), 0, s, pmax, z.nb, info + 1);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
