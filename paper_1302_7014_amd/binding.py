@@ -38,7 +38,7 @@ class PeelError(RuntimeError):
 
 
 class IbltDesc(C.Structure):
-    _fields_ = [("ncells", C.c_uint64), ("r", C.c_uint32), ("reserved", C.c_uint32),
+    _fields_ = [("ncells", C.c_uint64), ("r", C.c_uint32), ("workgroups", C.c_uint32),
                 ("seed", C.c_uint64)]
 
 
@@ -163,8 +163,9 @@ def peel_kcore(edges: torch.Tensor, n: int, k: int, csr: Csr, max_rounds: int = 
     return out
 
 
-def iblt_desc(ncells: int, r: int, seed: int) -> IbltDesc:
-    return IbltDesc(ncells, r, 0, seed & 0xFFFFFFFFFFFFFFFF)
+def iblt_desc(ncells: int, r: int, seed: int, workgroups: int = 0) -> IbltDesc:
+    """``workgroups``: iblt_list's persistent workgroups (0 = one per CU)."""
+    return IbltDesc(ncells, r, workgroups, seed & 0xFFFFFFFFFFFFFFFF)
 
 
 def iblt_table(ncells: int, device) -> torch.Tensor:
@@ -210,7 +211,7 @@ def iblt_list(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = None,
 # ---------------------------------------------------------------------------
 # Batched listing.
 
-BATCH_ENTRY = [("ncells", "<u8"), ("r", "<u4"), ("reserved", "<u4"), ("seed", "<u8"),
+BATCH_ENTRY = [("ncells", "<u8"), ("r", "<u4"), ("workgroups", "<u4"), ("seed", "<u8"),
                ("cells", "<u8"), ("out_keys", "<u8"), ("out_cap", "<u8"),
                ("round_stats", "<u8"), ("summary", "<u8")]
 

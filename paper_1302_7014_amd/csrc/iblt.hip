@@ -675,9 +675,11 @@ struct ListLayout {
   uint32_t grid, cb;
 };
 
-ListLayout list_layout(uint64_t ncells) {
+// grid: the persistent workgroups asked for (0 = one per CU; at most one per CU).
+ListLayout list_layout(uint64_t ncells, uint32_t want) {
   ListLayout L{};
-  L.grid = static_cast<uint32_t>(device_info().cus);  // one 1024-thread workgroup per CU
+  const uint32_t cus = static_cast<uint32_t>(device_info().cus);  // 1024-thread workgroups
+  L.grid = (want == 0 || want > cus) ? cus : want;
   L.cb = static_cast<uint32_t>((ncells + L.grid - 1) / L.grid + 4096);
   const uint64_t slots = (uint64_t)L.grid * L.cb;
   L.ctrl = align_up(sizeof(ListCtrl));
@@ -746,7 +748,7 @@ extern "C" peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, cons
 }
 
 extern "C" size_t iblt_list_workspace(const iblt_desc *desc) {
-  return desc_ok(desc) ? list_layout(desc->ncells).total : 0;
+  return desc_ok(desc) ? list_layout(desc->ncells, desc->workgroups).total : 0;
 }
 
 extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
@@ -756,7 +758,7 @@ extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64
       max_rounds == 0)
     return PEEL_EINVAL;
   if (reinterpret_cast<uintptr_t>(cells) % 32) return PEEL_EINVAL;
-  const ListLayout L = list_layout(desc->ncells);
+  const ListLayout L = list_layout(desc->ncells, desc->workgroups);
   if (ws_bytes < L.total) return PEEL_ENOSPC;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char *base = static_cast<char *>(ws);

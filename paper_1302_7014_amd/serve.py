@@ -10,9 +10,10 @@ first served as arena space frees up, and runs the GPU as a pipeline:
   table), overlapping whatever listing is running;
 * listing, routed by table size: a table of more than ``small_cells`` cells is
   listed alone by ``iblt_list`` on one of ``large_lanes`` streams (taken in
-  turn), as soon as its insert is done.  Each such run forms its team from the
-  CUs that are free, and a run on a mid-sized table is bound by its per-round
-  barriers, so runs on several lanes overlap well.  The small tables that are
+  turn), as soon as its insert is done.  Each lane's runs use an equal share
+  of the CUs, so runs on all lanes are resident together; a run on a
+  mid-sized table is bound by its per-round barriers, and runs on several
+  lanes overlap well.  The small tables that are
   inserted and not yet listed are listed together in one
   ``iblt_list_batched`` launch (one workgroup per table) on a small-lane
   stream, up to ``max_inflight`` such launches at once.  One workgroup lists a
@@ -178,10 +179,15 @@ class ContinuousServer(_Base):
         self.insert_stream = torch.cuda.Stream(device=self.device)
         self.list_streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
         self.admit_group = admit_group
-        # each large lane: a stream and a listing workspace for the largest table
+        # each large lane: a stream, an equal share of the CUs for its listing's
+        # persistent workgroups (so that every lane's run gets its whole team at
+        # once), and a listing workspace for the largest table
+        cus = torch.cuda.get_device_properties(self.device).multi_processor_count
+        self.lane_workgroups = max(1, cus // large_lanes)
         self.large_streams = [torch.cuda.Stream(device=self.device) for _ in range(large_lanes)]
-        self.large_ws = [pk.workspace(pk.iblt_list_workspace(pk.iblt_desc(max_cells, 3, 0)),
-                                      self.device) for _ in range(large_lanes)]
+        self.large_ws = [pk.workspace(pk.iblt_list_workspace(
+            pk.iblt_desc(max_cells, 3, 0, self.lane_workgroups)), self.device)
+            for _ in range(large_lanes)]
         # one batched-listing workspace per in-flight launch, sized for the largest small table
         self.ws = [pk.workspace(pk.iblt_list_batched_workspace(1 << 16, min(small_cells, max_cells)),
                                 self.device) for _ in range(max_inflight)]
@@ -192,8 +198,9 @@ class ContinuousServer(_Base):
         s = self.large_streams[lane]
         s.wait_event(q._event)
         t = q._table
+        d = pk.iblt_desc(t.desc.ncells, t.desc.r, t.desc.seed, self.lane_workgroups)
         with torch.cuda.stream(s):
-            pk.iblt_list(t.desc, t.cells, max_rounds=self.max_rounds,
+            pk.iblt_list(d, t.cells, max_rounds=self.max_rounds,
                          out=pk.ListOut(t.keys, t.round_stats, t.summary),
                          ws=self.large_ws[lane], stream=s)
         ev = torch.cuda.Event()

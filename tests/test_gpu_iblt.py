@@ -112,6 +112,30 @@ def test_list_limits():
         assert o.status == native.EROUNDS and g["flags"] & 0x2
 
 
+@pytest.mark.parametrize("wg", [1, 3, 64])
+def test_list_with_fewer_workgroups(wg):
+    # a listing given a share of the CUs: same rounds and keys as the oracle
+    need_gpu()
+    ncells = (1 << 17) + 77
+    keys = gen.distinct_keys(int(0.75 * ncells), 77 + wg)
+    d, cells = gpu_insert(ncells, 3, 9, keys)
+    d = pk.iblt_desc(ncells, 3, 9, workgroups=wg)
+    say("list workgroups", wg)
+    out = pk.iblt_list(d, cells, max_rounds=4096)
+    torch.cuda.synchronize()
+    s = out.summary.cpu().numpy()
+    o = native.iblt_list_rounds(native.iblt_insert(ncells, 3, 9, keys), max_rounds=4096)
+    assert 1 <= int(s[4]) <= wg
+    assert int(s[0]) == o.keys.size and int(s[1]) == o.rounds and int(s[3]) == 0
+    K = host_u64(out.round_stats)[: int(s[1])]
+    assert np.array_equal(K, o.K)
+    ks = host_u64(out.keys)[: int(s[0])]
+    off = 0
+    for kk, want in zip(K.tolist(), o.per_round()):
+        assert np.array_equal(np.sort(ks[off: off + kk]), want)
+        off += kk
+
+
 def test_corrupt_cell():
     need_gpu()
     ncells = 1 << 12
