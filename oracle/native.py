@@ -41,13 +41,14 @@ def lib():
         L.orc_splitmix64.argtypes = [u64, u64]
         L.orc_splitmix64.restype = u64
         L.orc_peel_rounds.argtypes = [u32, u64, u32, u32, P, u32, P, P, P, P, P, P, P]
+        L.orc_peel_subrounds.argtypes = [u32, u64, u32, u32, P, u32, P, P, P, P, P, P, P]
         L.orc_peel_queue.argtypes = [u32, u64, u32, u32, P, u64, P, P]
         L.orc_core_brute.argtypes = [u32, u64, u32, u32, P, P, P]
         L.orc_iblt_cells_of.argtypes = [u64, u32, u64, P, u64, P, P]
         L.orc_iblt_update.argtypes = [u64, u32, u64, P, P, P, P, u64, i32]
         L.orc_iblt_list_rounds.argtypes = [u64, u32, u64, P, P, P, P, u64, P, u32, P, P, P]
         L.orc_iblt_list_seq.argtypes = [u64, u32, u64, P, P, P, P, u64, P]
-        for f in ("orc_peel_rounds", "orc_peel_queue", "orc_core_brute", "orc_iblt_cells_of",
+        for f in ("orc_peel_rounds", "orc_peel_subrounds", "orc_peel_queue", "orc_core_brute", "orc_iblt_cells_of",
                   "orc_iblt_update", "orc_iblt_list_rounds", "orc_iblt_list_seq"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -97,6 +98,27 @@ def peel_rounds(n: int, edges, k: int, max_rounds: int = 1 << 20) -> PeelResult:
                                _p(V), _p(E), C.byref(R), C.byref(Re))
     if st not in (OK, EROUNDS):
         raise RuntimeError(f"orc_peel_rounds failed: {st}")
+    return PeelResult(st, vr, er, deg, V[: R.value].copy(), E[: R.value].copy(), R.value, Re.value)
+
+
+def peel_subrounds(n: int, edges, k: int, max_rounds: int = 1 << 20) -> PeelResult:
+    """Peeling with subtables (Appendix B): r subrounds per round, subround (i, j)
+    removing the vertices of subtable j below degree k.  Rounds in the result are
+    subrounds, numbered (i-1) r + j from 1."""
+    e = _edges(edges)
+    m, r = e.shape
+    vr = np.zeros(n, np.uint32)
+    er = np.zeros(m, np.uint32)
+    deg = np.zeros(n, np.uint32)
+    cap = min(max_rounds, r * (n + 1)) + 1
+    V = np.zeros(cap, np.uint64)
+    E = np.zeros(cap, np.uint64)
+    R = C.c_uint32(0)
+    Re = C.c_uint32(0)
+    st = lib().orc_peel_subrounds(n, m, r, k, _p(e), min(max_rounds, cap - 1), _p(vr), _p(er),
+                                  _p(deg), _p(V), _p(E), C.byref(R), C.byref(Re))
+    if st not in (OK, EROUNDS):
+        raise RuntimeError(f"orc_peel_subrounds failed: {st}")
     return PeelResult(st, vr, er, deg, V[: R.value].copy(), E[: R.value].copy(), R.value, Re.value)
 
 

@@ -189,6 +189,90 @@ int orc_peel_rounds(uint32_t n, uint64_t m, uint32_t r, uint32_t k,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Peeling with subtables (Appendix B): the vertex ids are split into r      */
+/* consecutive subtables of near-equal size (the first n mod r one larger),  */
+/* and each round is r subrounds; subround (i, j) removes, at once, every    */
+/* alive vertex of subtable j whose degree is below k at the start of the    */
+/* subround, with the edges it still holds.  Subrounds are numbered          */
+/* s = (i-1) r + j from 1 and an empty subround still takes its number; the  */
+/* run ends after r empty subrounds in a row (no subtable has a vertex to    */
+/* remove).  Outputs as orc_peel_rounds, per subround; *rounds_out is the    */
+/* last subround that removed a vertex.                                      */
+
+int orc_peel_subrounds(uint32_t n, uint64_t m, uint32_t r, uint32_t k,
+                       const uint32_t *edges, uint32_t max_rounds,
+                       uint32_t *vertex_round, uint32_t *edge_round,
+                       uint32_t *deg_out, uint64_t *V, uint64_t *E,
+                       uint32_t *rounds_out, uint32_t *edge_rounds_out)
+{
+    orc_incidence g;
+    uint32_t *deg, *frontier, *lo;
+    uint64_t *killed;
+    uint64_t i, v;
+    uint32_t s, j, empty = 0, last_v = 0, last_e = 0;
+    int rc;
+
+    if (n == 0 || r < 2 || r > 8 || k == 0) return ORC_EINVAL;
+    rc = orc_incidence_build(n, m, r, edges, &g);
+    if (rc) return rc;
+    deg = (uint32_t *)calloc(n, sizeof(uint32_t));
+    frontier = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    killed = (uint64_t *)malloc((size_t)(m ? m : 1) * sizeof(uint64_t));
+    lo = (uint32_t *)malloc((r + 1) * sizeof(uint32_t));
+    if (!deg || !frontier || !killed || !lo) {
+        free(deg); free(frontier); free(killed); free(lo); orc_incidence_free(&g);
+        return ORC_ENOMEM;
+    }
+    /* subtable j holds ids lo[j] .. lo[j+1]-1 */
+    lo[0] = 0;
+    for (j = 0; j < r; j++) lo[j + 1] = lo[j] + n / r + (j < n % r ? 1u : 0u);
+    for (i = 0; i < m * (uint64_t)r; i++) deg[edges[i]]++;
+    memset(vertex_round, 0, (size_t)n * sizeof(uint32_t));
+    memset(edge_round, 0, (size_t)m * sizeof(uint32_t));
+
+    rc = ORC_OK;
+    for (s = 1;; s++) {
+        uint64_t nf = 0, ne = 0;
+        j = (s - 1) % r;
+        for (v = lo[j]; v < lo[j + 1]; v++)
+            if (vertex_round[v] == 0 && deg[v] < k) frontier[nf++] = (uint32_t)v;
+        if (nf == 0) {
+            if (s <= max_rounds) { V[s - 1] = 0; E[s - 1] = 0; }
+            if (++empty == r) break;
+            continue;
+        }
+        empty = 0;
+        if (s > max_rounds) { rc = ORC_EROUNDS; break; }
+        for (i = 0; i < nf; i++) vertex_round[frontier[i]] = s;
+        for (i = 0; i < nf; i++) {
+            uint32_t u = frontier[i];
+            uint64_t p;
+            for (p = g.start[u]; p < g.start[u + 1]; p++) {
+                uint64_t e = g.edge[p];
+                if (edge_round[e] == 0) {
+                    edge_round[e] = s;
+                    killed[ne++] = e;
+                }
+            }
+        }
+        for (i = 0; i < ne; i++) {
+            uint32_t q;
+            for (q = 0; q < r; q++) deg[edges[killed[i] * r + q]]--;
+        }
+        V[s - 1] = nf;
+        E[s - 1] = ne;
+        last_v = s;
+        if (ne) last_e = s;
+    }
+    memcpy(deg_out, deg, (size_t)n * sizeof(uint32_t));
+    *rounds_out = last_v;
+    *edge_rounds_out = last_e;
+    free(deg); free(frontier); free(killed); free(lo);
+    orc_incidence_free(&g);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Sequential peeling process (Section 1): repeatedly remove one vertex of   */
 /* degree < k with its edges.  order_seed == 0 pops in FIFO order; any other */
 /* value pops a uniformly chosen queued vertex (used to check that the core  */
