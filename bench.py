@@ -94,7 +94,7 @@ class Timer:
         self._pending = []
 
 
-def bench_kcore(spec, steps, warmup):
+def bench_kcore(spec, steps, warmup, subtables=False):
     log(f"generating {spec.name}: n={spec.n} m={spec.m} r={spec.r}")
     e_host = spec.edges(1)
     dev = torch.device("cuda", 0)
@@ -118,10 +118,12 @@ def bench_kcore(spec, steps, warmup):
             with tb:
                 pk.hg_build(e, n, out=csr, ws=ws_b)
             with tp:
-                pk.peel_kcore(e, n, spec.k, csr, max_rounds=max_rounds, out=out, ws=ws_p)
+                pk.peel_kcore(e, n, spec.k, csr, max_rounds=max_rounds, out=out, ws=ws_p,
+                              subtables=subtables)
         else:
             pk.hg_build(e, n, out=csr, ws=ws_b)
-            pk.peel_kcore(e, n, spec.k, csr, max_rounds=max_rounds, out=out, ws=ws_p)
+            pk.peel_kcore(e, n, spec.k, csr, max_rounds=max_rounds, out=out, ws=ws_p,
+                          subtables=subtables)
 
     for _ in range(warmup):
         step(False)
@@ -390,6 +392,12 @@ def main():
         "rounds": kc["rounds"], "edge_rounds": kc["edge_rounds"],
         "core_vertices": kc["core_vertices"],
     }
+    # the paper's own schedule (peeling with subtables) on the same workload
+    sb = bench_kcore(spec, max(3, args.steps // 2), 1, subtables=True)
+    extra["subtables"] = {
+        "peel_ms": sb["peel_ms"], "subrounds": sb["rounds"], "edge_subrounds": sb["edge_rounds"],
+        "peel_edges_per_s": sb["m_removed"] / (sb["peel_ms"] * 1e-3),
+        "vs_rounds_peel_ms": kc["peel_ms"]}
     if not args.no_batched:
         log("batched IBLT listing (4096 tables)")
         extra["batched"] = bench_batched(configs.batched_main(), 3)

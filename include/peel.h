@@ -122,6 +122,28 @@ peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n
                        uint32_t max_rounds, uint32_t *summary, void *ws, size_t ws_bytes,
                        void *stream);
 
+/*
+ * Peeling with subtables (Appendix B): the process the paper's GPU code runs.
+ * The vertex ids are split into r consecutive subtables of near-equal size
+ * (the first n mod r one larger), and every round is r subrounds: subround
+ * (i, j) removes, at once, each alive vertex of subtable j whose degree is
+ * below k at the start of the subround, with every alive edge it holds.
+ * Subrounds are numbered s = (i-1) r + j from 1, an empty subround keeping its
+ * number; the run ends when no subtable has a vertex to remove.  It ends at
+ * the same k-core as peel_kcore.
+ *
+ * Arguments, outputs and errors are those of peel_kcore, with "round" read as
+ * "subround": vertex_round and edge_round hold subround numbers, round_stats
+ * has one entry pair per subround (0 for an empty one), max_rounds bounds the
+ * subrounds, and summary[0] is the last subround that removed a vertex.  The
+ * workspace is peel_kcore_workspace(n, m, r).
+ */
+peel_status peel_kcore_subtables(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n,
+                                 uint32_t k, const uint32_t *offsets, const uint32_t *inc,
+                                 uint32_t *deg, uint32_t *vertex_round, uint32_t *edge_round,
+                                 uint64_t *round_stats, uint32_t max_rounds, uint32_t *summary,
+                                 void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Invertible Bloom Lookup Table (Section 5).                                */
 /*

@@ -27,7 +27,8 @@ FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT = 0x1, 0x2, 
 
 # Every symbol include/peel.h declares.
 EXPORTS = ("peel_strerror", "peel_abi_version", "hg_build_workspace", "hg_build",
-           "peel_kcore_workspace", "peel_kcore", "iblt_insert", "iblt_list_workspace", "iblt_list",
+           "peel_kcore_workspace", "peel_kcore", "peel_kcore_subtables", "iblt_insert",
+           "iblt_list_workspace", "iblt_list",
            "iblt_list_batched_workspace", "iblt_list_batched")
 
 _lib = None
@@ -59,6 +60,7 @@ def lib() -> C.CDLL:
         L.peel_kcore_workspace.argtypes = [u32, u64, u32]
         L.peel_kcore_workspace.restype = sz
         L.peel_kcore.argtypes = [P, u64, u32, u32, u32, P, P, P, P, P, P, u32, P, P, sz, P]
+        L.peel_kcore_subtables.argtypes = L.peel_kcore.argtypes
         L.iblt_insert.argtypes = [C.POINTER(IbltDesc), P, P, u64, P]
         L.iblt_list_workspace.argtypes = [C.POINTER(IbltDesc)]
         L.iblt_list_workspace.restype = sz
@@ -66,7 +68,8 @@ def lib() -> C.CDLL:
         L.iblt_list_batched_workspace.argtypes = [u32, u64]
         L.iblt_list_batched_workspace.restype = sz
         L.iblt_list_batched.argtypes = [P, u32, u64, u32, C.POINTER(BatchSchedule), P, sz, P]
-        for f in ("hg_build", "peel_kcore", "iblt_insert", "iblt_list", "iblt_list_batched"):
+        for f in ("hg_build", "peel_kcore", "peel_kcore_subtables", "iblt_insert", "iblt_list",
+                  "iblt_list_batched"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -143,11 +146,13 @@ def peel_kcore_workspace(n: int, m: int, r: int) -> int:
 
 
 def peel_kcore(edges: torch.Tensor, n: int, k: int, csr: Csr, max_rounds: int = 4096,
-               out: PeelOut | None = None, ws: torch.Tensor | None = None, stream=None) -> PeelOut:
+               out: PeelOut | None = None, ws: torch.Tensor | None = None, stream=None,
+               subtables: bool = False) -> PeelOut:
     """Round-synchronous peel to the k-core; ``csr.deg`` is consumed (see ``out.deg``).
 
     ``out.deg`` is ``csr.deg`` itself unless ``out`` brings its own degrees
-    (then the caller copies the initial degrees into it).
+    (then the caller copies the initial degrees into it).  ``subtables=True``
+    calls peel_kcore_subtables: rounds are then subrounds.
     """
     m, r = edges.shape
     dev = edges.device
@@ -156,10 +161,11 @@ def peel_kcore(edges: torch.Tensor, n: int, k: int, csr: Csr, max_rounds: int = 
                       _empty(2 * max_rounds, torch.int64, dev), _empty(8, torch.int32, dev))
     if ws is None:
         ws = workspace(peel_kcore_workspace(n, m, r), dev)
-    _check(lib().peel_kcore(_ptr(edges), m, r, n, k, _ptr(csr.offsets), _ptr(csr.inc),
-                            _ptr(out.deg), _ptr(out.vertex_round), _ptr(out.edge_round),
-                            _ptr(out.round_stats), max_rounds, _ptr(out.summary), _ptr(ws),
-                            ws.numel(), _stream(stream)), "peel_kcore")
+    fn = lib().peel_kcore_subtables if subtables else lib().peel_kcore
+    _check(fn(_ptr(edges), m, r, n, k, _ptr(csr.offsets), _ptr(csr.inc),
+              _ptr(out.deg), _ptr(out.vertex_round), _ptr(out.edge_round),
+              _ptr(out.round_stats), max_rounds, _ptr(out.summary), _ptr(ws),
+              ws.numel(), _stream(stream)), "peel_kcore_subtables" if subtables else "peel_kcore")
     return out
 
 

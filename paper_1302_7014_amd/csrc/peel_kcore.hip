@@ -106,7 +106,17 @@ struct PeelArgs {
   uint32_t max_rounds;
   uint32_t force_global;  // PEEL_ENGINE=global: skip the owner engine (testing)
   uint32_t round_policy;  // PEEL_ROUNDS=sparse (default) | dense | auto (chosen per round)
+  uint32_t subtables;     // 1: peeling with subtables, rounds are subrounds
+  uint32_t sub_lo[9];     // subtable j holds the vertices sub_lo[j] .. sub_lo[j+1]-1
 };
+
+// The subtable of vertex v (subtables mode).
+__device__ inline uint32_t subtable_of_vertex(const PeelArgs &a, uint32_t r, uint32_t v) {
+  uint32_t j = 0;
+  for (uint32_t i = 1; i < r; ++i)
+    if (v >= a.sub_lo[i]) j = i;
+  return j;
+}
 
 __global__ void k_peel_init(PeelCtrl *ctrl) {
   uint32_t *w = reinterpret_cast<uint32_t *>(ctrl);
@@ -145,7 +155,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   __shared__ uint32_t s_pre[kOT];
   __shared__ uint32_t scan_lds[kOT / kWave + 1];
   __shared__ uint32_t fbl[kOwnMaxV / 32];  // the next frontier, as bits over my vertices
-  __shared__ uint32_t s_n, s_w;
+  __shared__ uint32_t s_n, s_w, s_p;
 
   PeelCtrl *ctrl = a.ctrl;
   uint32_t slot, T;
@@ -171,6 +181,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   uint32_t *myDecs = a.qdec + a.offsets[v0];
 
   // ---- init: LDS degrees, alive bits, outputs, F_1 --------------------------
+  if (tid == 0) s_p = 0;
   for (uint32_t w = tid; w < Vb / 32; w += kOT) {
     gone[w] = 0;
     fbl[w] = 0;
@@ -195,7 +206,10 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       }
     }
     deg8[w] = word;
-    if (low) atomicOr(&fbl[w >> 3], low << (4 * (w & 7)));
+    if (low) {
+      atomicOr(&fbl[w >> 3], low << (4 * (w & 7)));
+      atomicAdd(&s_p, static_cast<uint32_t>(__popc(low)));
+    }
   }
   for (uint64_t e = e0 + tid; e < e1; e += kOT) a.er[e] = 0;
   if (slot == 0)
@@ -203,6 +217,11 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   if (tid == 0) s_n = ~0u;  // F_1 is taken from the bitmap
   __syncthreads();
   uint32_t fcnt = 0;
+  // Subtables mode: subround t takes only the frontier bits of subtable
+  // (t-1) mod R; the bits of the other subtables wait in the bitmap.  `pend`
+  // counts my waiting bits, so that the run ends when no workgroup has any.
+  const bool sub = a.subtables != 0;
+  uint32_t pend = s_p;
 
   // v leaves in round t with every edge it still holds, so its final degree
   // is 0; its byte now keeps the round (vertex_round is written at the end)
@@ -222,6 +241,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   uint64_t removed = 0;
   uint64_t alive_m = m;  // edges alive at the start of the round
   uint64_t prev_v = 0;   // |F_{t-1}|
+  uint32_t last = 0;     // the last round that removed a vertex
   uint32_t t = 1;
   for (;; ++t) {
     const bool over = t > a.max_rounds;
@@ -236,7 +256,8 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     // only when asked for (every round, or chosen per round by the size of the
     // last frontier against the alive edges).  Every workgroup takes the same
     // decision from the same global counts.
-    const bool dense = a.round_policy == kRoundsAuto ? (t == 1 || prev_v * kDenseRatio >= alive_m)
+    const bool dense = sub ? false
+                     : a.round_policy == kRoundsAuto ? (t == 1 || prev_v * kDenseRatio >= alive_m)
                                                       : a.round_policy == kRoundsDense;
     // ---- F_t in vertex order: the bitmap is compacted into myF (and cleared for
     // F_{t+1}); a dense round also publishes it.  Walking F_t in vertex order
@@ -245,7 +266,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     // decrement phase: it is taken from there (its bits cleared one by one)
     // instead of scanning the whole bitmap.
     const bool publish = dense && !over;
-    if (s_n <= (uint32_t)kOT && !publish) {
+    if (!sub && s_n <= (uint32_t)kOT && !publish) {
       fcnt = s_n;
       for (uint32_t i = tid; i < fcnt; i += kOT) {
         const uint32_t v = s_start[i];
@@ -254,14 +275,27 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       }
       __syncthreads();
     } else {
-      const uint32_t nw = (v1 - v0 + 31) / 32;
+      // the vertices [x0, x1) whose bits are taken: all of mine, or in
+      // subtables mode those of this subround's subtable
+      uint32_t x0 = v0, x1 = v1;
+      if (sub) {
+        const uint32_t j = (t - 1) % R;
+        x0 = a.sub_lo[j] > v0 ? a.sub_lo[j] : v0;
+        x1 = a.sub_lo[j + 1] < v1 ? a.sub_lo[j + 1] : v1;
+        if (x1 < x0) x1 = x0;
+      }
+      const uint32_t wlo = (x0 - v0) >> 5, whi = (x1 - v0 + 31) >> 5;
       fcnt = 0;
-      for (uint32_t w0 = 0; w0 < nw; w0 += kOT) {
+      for (uint32_t w0 = wlo; w0 < whi; w0 += kOT) {
         const uint32_t w = w0 + tid;
         uint32_t bits = 0;
-        if (w < nw) {
-          bits = fbl[w];
-          fbl[w] = 0;
+        if (w < whi) {
+          const uint32_t base = v0 + 32 * w;
+          const uint32_t b0 = x0 > base ? x0 - base : 0u;
+          const uint32_t b1 = x1 - base < 32u ? x1 - base : 32u;
+          const uint32_t mask = (b1 == 32u ? ~0u : (1u << b1) - 1u) & ~((1u << b0) - 1u);
+          bits = fbl[w] & mask;
+          fbl[w] &= ~mask;
           if (publish) a.fbits[v0 / 32 + w] = bits;
         }
         uint32_t tot;
@@ -336,14 +370,22 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         a.qclaim[atomicAdd(&cur[e / Eb], 1u)] = e;
       }
     }
-    uint64_t vt;
-    if (!sum_barrier(&ctrl->bar, T, slot, fcnt, &epoch, a.limit, &vt, ctrl->stamp)) return;
-    if (vt == 0) break;
+    // The barrier sums |F_t| and, in subtables mode, the waiting bits (high word).
+    pend -= sub ? fcnt : 0u;
+    uint64_t tot;
+    const uint64_t mine = sub ? ((uint64_t)pend << 32 | fcnt) : (uint64_t)fcnt;
+    if (!sum_barrier(&ctrl->bar, T, slot, mine, &epoch, a.limit, &tot, ctrl->stamp)) return;
+    const uint64_t vt = sub ? (tot & 0xffffffffull) : tot;
+    const uint64_t waiting = sub ? (tot >> 32) : 0u;
+    if (vt == 0 && waiting == 0) break;
     if (over) {
-      // F_t stays in the graph: the outputs hold the state after max_rounds rounds.
+      // F_t (or a later subround's frontier) stays in the graph: the outputs
+      // hold the state after max_rounds rounds.
       if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_EROUNDS);
       break;
     }
+    if (vt == 0) continue;  // subtables mode: an empty subround
+    last = t;
     removed += vt;
     if (slot == 0 && tid == 0) a.stats[2ull * (t - 1)] = vt;
 
@@ -519,6 +561,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       }
     }
     __syncthreads();
+    if (sub) pend += s_n;
   }
 
   // ---- epilogue: removal rounds and final degrees, written in order ----------
@@ -534,7 +577,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     }
   }
   if (slot == 0 && tid == 0) {
-    ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
+    ctrl->rounds = last;
     ctrl->removed = removed;
     ctrl->team = T;
     ctrl->mode = kModeOwnerDone;
@@ -559,6 +602,10 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
   if (!team_join(&ctrl->team_glob, a.quiet, a.limit, &slot, &nblocks)) return;
   const uint64_t gtid = (uint64_t)slot * kBlock + threadIdx.x;
   const uint64_t gsize = (uint64_t)nblocks * kBlock;
+  // Subtables mode: the list of round t holds every waiting vertex; those whose
+  // subround (vertex_round, set when they fell below k) is not t move on to the
+  // next list unchanged.
+  const bool sub = a.subtables != 0;
 
   // ---- phase 0 ------------------------------------------------------------
   for (uint64_t e = gtid; e < a.m; e += gsize) a.er[e] = 0;
@@ -571,7 +618,8 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
       const uint64_t v = base + i;
       if (v < a.n) {
         const uint32_t is_low = a.deg[v] < a.k ? 1u : 0u;
-        a.vr[v] = is_low;
+        // the (sub)round in which v leaves: 1, or its subtable's first subround
+        a.vr[v] = is_low ? (sub ? subtable_of_vertex(a, R, (uint32_t)v) + 1u : 1u) : 0u;
         low |= is_low << i;
         cnt += is_low;
       }
@@ -590,30 +638,41 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
 
   // ---- rounds -------------------------------------------------------------
   uint32_t t = 1;
+  uint32_t last = 0;
   uint64_t removed = 0;
   for (;; ++t) {
     const uint32_t size = atomic_load_u32(&ctrl->fcount[t % 3]);
     const uint32_t *cur = (t & 1u) ? a.fa : a.fb;
     if (size == 0) break;
     if (t > a.max_rounds) {
-      // Leave the state after max_rounds rounds: F_t stays in the graph.
+      // Leave the state after max_rounds rounds: F_t (and, with subtables, every
+      // waiting vertex) stays in the graph.
       for (uint64_t i = gtid; i < size; i += gsize) a.vr[cur[i]] = 0;
       if (gtid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_EROUNDS);
       break;
     }
-    removed += size;
     uint32_t *nxt = (t & 1u) ? a.fb : a.fa;
     uint32_t *ncount = &ctrl->fcount[(t + 1) % 3];
-    if (gtid == 0) {
-      a.stats[2ull * (t - 1)] = size;
-      ctrl->fcount[(t + 2) % 3] = 0;
-    }
+    if (gtid == 0) ctrl->fcount[(t + 2) % 3] = 0;
     if (threadIdx.x == 0) qn = 0;
     __syncthreads();
 
-    uint32_t wins = 0;
+    auto push = [&](uint32_t u) {
+      const uint32_t slotq = atomicAdd(&qn, 1u);
+      if (slotq < kQueue)
+        q[slotq] = u;
+      else
+        nxt[atomicAdd(ncount, 1u)] = u;
+    };
+    const uint32_t jt = (t - 1) % R;
+    uint32_t wins = 0, taken = 0;
     for (uint64_t i = gtid; i < size; i += gsize) {
       const uint32_t v = cur[i];
+      if (sub && a.vr[v] != t) {  // waits for its subtable's subround
+        push(v);
+        continue;
+      }
+      ++taken;
       const uint32_t beg = a.offsets[v];
       const uint32_t end = a.offsets[v + 1];
       for (uint32_t p = beg; p < end; ++p) {
@@ -633,13 +692,10 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
           if (u >= a.n) continue;  // ids >= n are reported by hg_build and skipped here
           const uint32_t old = atomicSub(&a.deg[u], 1u);
           if (old == a.k) {
-            a.vr[u] = t + 1;
-            const uint32_t slotq = atomicAdd(&qn, 1u);
-            if (slotq < kQueue) {
-              q[slotq] = u;
-            } else {
-              nxt[atomicAdd(ncount, 1u)] = u;
-            }
+            // next round, or the next subround of u's subtable (a full round
+            // later when that is the subtable of this subround)
+            a.vr[u] = sub ? t + (subtable_of_vertex(a, R, u) + R - jt - 1) % R + 1u : t + 1u;
+            push(u);
           }
         }
       }
@@ -650,11 +706,19 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nq; i += kBlock) nxt[s_base + i] = q[i];
     const uint32_t bw = block_sum(wins, lds);
+    const uint32_t bt = block_sum(taken, lds);
     if (threadIdx.x == 0 && bw) atomicAdd(&a.stats[2ull * (t - 1) + 1], (uint64_t)bw);
+    if (threadIdx.x == 0 && bt) atomicAdd(&a.stats[2ull * (t - 1)], (uint64_t)bt);
     if (!grid_barrier(&ctrl->sync, nblocks, a.limit, ctrl->stamp)) return;
+    const uint64_t vt = __hip_atomic_load(&a.stats[2ull * (t - 1)], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    if (vt) {
+      last = t;
+      removed += vt;
+    }
   }
   if (gtid == 0) {
-    ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
+    ctrl->rounds = last;
     ctrl->removed = removed;
     ctrl->team = nblocks;
   }
@@ -732,11 +796,14 @@ extern "C" size_t peel_kcore_workspace(uint32_t n, uint64_t m, uint32_t r) {
   return layout(n, m, r).total;
 }
 
-extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n,
-                                  uint32_t k, const uint32_t *offsets, const uint32_t *inc,
-                                  uint32_t *deg, uint32_t *vertex_round, uint32_t *edge_round,
-                                  uint64_t *round_stats, uint32_t max_rounds, uint32_t *summary,
-                                  void *ws, size_t ws_bytes, void *stream) {
+namespace peel {
+namespace {
+
+peel_status peel_run(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n, uint32_t k,
+                     const uint32_t *offsets, const uint32_t *inc, uint32_t *deg,
+                     uint32_t *vertex_round, uint32_t *edge_round, uint64_t *round_stats,
+                     uint32_t max_rounds, uint32_t *summary, void *ws, size_t ws_bytes,
+                     void *stream, bool subtables) {
   if (r < 2 || r > 8 || n == 0 || k == 0 || max_rounds == 0) return PEEL_EINVAL;
   if (m * (uint64_t)r >= (1ull << 32)) return PEEL_EINVAL;
   if ((m && (!edges || !inc || !edge_round)) || !offsets || !deg || !vertex_round ||
@@ -780,6 +847,10 @@ extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r,
                    : std::strcmp(rounds, "dense") == 0 ? kRoundsDense
                    : std::strcmp(rounds, "auto") == 0  ? kRoundsAuto
                                                         : kRoundsSparse;
+  a.subtables = subtables ? 1u : 0u;
+  a.sub_lo[0] = 0;
+  for (uint32_t j = 0; j < 8; ++j)
+    a.sub_lo[j + 1] = a.sub_lo[j] + (j < r ? n / r + (j < n % r ? 1u : 0u) : 0u);
 
   hipLaunchKernelGGL(k_peel_init, dim3(1), dim3(256), 0, s, a.ctrl);
   PEEL_HIP_TRY(hipGetLastError());
@@ -797,4 +868,27 @@ extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r,
   hipLaunchKernelGGL(k_peel_finish, dim3(1), dim3(64), 0, s, a.ctrl, round_stats, n, summary);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
+}
+
+}  // namespace
+}  // namespace peel
+
+extern "C" peel_status peel_kcore(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n,
+                                  uint32_t k, const uint32_t *offsets, const uint32_t *inc,
+                                  uint32_t *deg, uint32_t *vertex_round, uint32_t *edge_round,
+                                  uint64_t *round_stats, uint32_t max_rounds, uint32_t *summary,
+                                  void *ws, size_t ws_bytes, void *stream) {
+  return peel_run(edges, m, r, n, k, offsets, inc, deg, vertex_round, edge_round, round_stats,
+                  max_rounds, summary, ws, ws_bytes, stream, false);
+}
+
+extern "C" peel_status peel_kcore_subtables(const uint32_t *edges, uint64_t m, uint32_t r,
+                                            uint32_t n, uint32_t k, const uint32_t *offsets,
+                                            const uint32_t *inc, uint32_t *deg,
+                                            uint32_t *vertex_round, uint32_t *edge_round,
+                                            uint64_t *round_stats, uint32_t max_rounds,
+                                            uint32_t *summary, void *ws, size_t ws_bytes,
+                                            void *stream) {
+  return peel_run(edges, m, r, n, k, offsets, inc, deg, vertex_round, edge_round, round_stats,
+                  max_rounds, summary, ws, ws_bytes, stream, true);
 }

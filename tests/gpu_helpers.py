@@ -37,15 +37,15 @@ def host_u64(t: torch.Tensor) -> np.ndarray:
     return t.cpu().numpy().view(np.uint64)
 
 
-def gpu_peel(n: int, edges: np.ndarray, k: int, max_rounds: int = 4096):
-    """hg_build + peel_kcore on the GPU; returns numpy results."""
+def gpu_peel(n: int, edges: np.ndarray, k: int, max_rounds: int = 4096, subtables: bool = False):
+    """hg_build + peel_kcore (or peel_kcore_subtables) on the GPU; returns numpy results."""
     e = dev_u32(edges.reshape(-1, edges.shape[1]) if edges.size else
                 np.zeros((0, edges.shape[1]), np.uint32))
     e = e.view(edges.shape[0], edges.shape[1])
     csr = pk.hg_build(e, n)
     deg0 = host_u32(csr.deg)[:n].copy()
     info = host_u32(csr.info)
-    out = pk.peel_kcore(e, n, k, csr, max_rounds=max_rounds)
+    out = pk.peel_kcore(e, n, k, csr, max_rounds=max_rounds, subtables=subtables)
     torch.cuda.synchronize()
     m = edges.shape[0]
     summ = host_u32(out.summary)
