@@ -47,9 +47,11 @@ def lib():
         L.orc_iblt_cells_of.argtypes = [u64, u32, u64, P, u64, P, P]
         L.orc_iblt_update.argtypes = [u64, u32, u64, P, P, P, P, u64, i32]
         L.orc_iblt_list_rounds.argtypes = [u64, u32, u64, P, P, P, P, u64, P, u32, P, P, P]
+        L.orc_iblt_list_subrounds.argtypes = L.orc_iblt_list_rounds.argtypes
         L.orc_iblt_list_seq.argtypes = [u64, u32, u64, P, P, P, P, u64, P]
         for f in ("orc_peel_rounds", "orc_peel_subrounds", "orc_peel_queue", "orc_core_brute", "orc_iblt_cells_of",
-                  "orc_iblt_update", "orc_iblt_list_rounds", "orc_iblt_list_seq"):
+                  "orc_iblt_update", "orc_iblt_list_rounds", "orc_iblt_list_subrounds",
+                  "orc_iblt_list_seq"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -224,6 +226,27 @@ def iblt_list_rounds(t: IbltTable, max_rounds: int = 1 << 20, out_cap: int | Non
                                     C.byref(R), C.byref(bad))
     if st not in (OK, EROUNDS, ENOSPC):
         raise RuntimeError(f"orc_iblt_list_rounds failed: {st}")
+    return ListResult(st, out[: nl.value].copy(), K[: R.value].copy(), R.value, bool(bad.value))
+
+
+def iblt_list_subrounds(t: IbltTable, max_rounds: int = 1 << 20,
+                        out_cap: int | None = None) -> ListResult:
+    """Listing with subtables (Section 5; Appendix B): r subrounds per round, each
+    listing the pure cells of one subtable; consumes ``t``.  Rounds in the result
+    are subrounds, numbered (i-1) r + j from 1."""
+    cap = t.ncells if out_cap is None else out_cap
+    out = np.zeros(max(cap, 1), np.uint64)
+    kcap = min(max_rounds, t.r * (t.ncells + 1)) + 1
+    K = np.zeros(kcap, np.uint64)
+    nl = C.c_uint64(0)
+    R = C.c_uint32(0)
+    bad = C.c_int32(0)
+    st = lib().orc_iblt_list_subrounds(t.ncells, t.r, t.seed, _p(t.count), _p(t.key_sum),
+                                       _p(t.hash_sum), _p(out), cap, _p(K),
+                                       min(max_rounds, kcap - 1), C.byref(nl), C.byref(R),
+                                       C.byref(bad))
+    if st not in (OK, EROUNDS, ENOSPC):
+        raise RuntimeError(f"orc_iblt_list_subrounds failed: {st}")
     return ListResult(st, out[: nl.value].copy(), K[: R.value].copy(), R.value, bool(bad.value))
 
 

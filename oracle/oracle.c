@@ -557,3 +557,68 @@ int orc_iblt_list_seq(uint64_t ncells, uint32_t r, uint64_t seed,
     *n_listed_out = n_listed;
     return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Listing with subtables (Section 5, "Implementation Details"; Appendix B):  */
+/* the paper's GPU process.  Each round is r subrounds; subround (i, j)       */
+/* lists the key of every cell of subtable j that is pure at the start of    */
+/* the subround (a key has one cell per subtable, so each key once) and      */
+/* deletes each of those keys from its r cells.  Subrounds are numbered      */
+/* s = (i-1) r + j from 1, an empty one keeping its number; the run ends     */
+/* after r empty subrounds in a row.  K[s-1] = keys listed in subround s;    */
+/* *rounds_out = the last subround that listed a key.  Limits as for         */
+/* orc_iblt_list_rounds.                                                     */
+
+int orc_iblt_list_subrounds(uint64_t ncells, uint32_t r, uint64_t seed,
+                            int32_t *count, uint64_t *key_sum, uint64_t *hash_sum,
+                            uint64_t *out_keys, uint64_t out_cap,
+                            uint64_t *K, uint32_t max_rounds,
+                            uint64_t *n_listed_out, uint32_t *rounds_out,
+                            int32_t *corrupt_out)
+{
+    orc_iblt t;
+    uint64_t n_listed = 0, c, *got;
+    uint32_t s, empty = 0;
+    int32_t corrupt = 0;
+    int rc = orc_iblt_setup(&t, ncells, r, seed);
+    if (rc) return rc;
+    got = (uint64_t *)malloc((size_t)ncells * sizeof(uint64_t));
+    if (!got) return ORC_ENOMEM;
+    *rounds_out = 0;
+    for (s = 1;; s++) {
+        uint32_t j = (s - 1) % r;
+        uint64_t nk = 0, i;
+        for (c = t.base[j]; c < t.base[j] + t.size[j]; c++) {
+            if (count[c] != 1) continue;
+            if (hash_sum[c] != orc_iblt_check(&t, key_sum[c])) { corrupt = 1; continue; }
+            got[nk++] = key_sum[c];
+        }
+        if (nk == 0) {
+            if (s <= max_rounds) K[s - 1] = 0;
+            if (++empty == r) break;
+            continue;
+        }
+        empty = 0;
+        if (s > max_rounds) { rc = ORC_EROUNDS; break; }
+        if (n_listed + nk > out_cap) { rc = ORC_ENOSPC; break; }
+        qsort(got, nk, sizeof(uint64_t), orc_cmp_u64);
+        for (i = 0; i < nk; i++) {
+            uint64_t x = got[i], h = orc_iblt_check(&t, x);
+            uint32_t q;
+            out_keys[n_listed + i] = x;
+            for (q = 0; q < r; q++) {
+                uint64_t cc = orc_iblt_cell(&t, q, x);
+                count[cc] -= 1;
+                key_sum[cc] ^= x;
+                hash_sum[cc] ^= h;
+            }
+        }
+        K[s - 1] = nk;
+        n_listed += nk;
+        *rounds_out = s;
+    }
+    free(got);
+    *n_listed_out = n_listed;
+    *corrupt_out = corrupt;
+    return rc;
+}

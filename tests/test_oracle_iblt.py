@@ -110,3 +110,50 @@ def test_out_capacity_and_round_limit():
     part = native.iblt_list_rounds(t.copy(), max_rounds=2)
     assert part.status == native.EROUNDS
     assert np.array_equal(part.K, full.K[:2])
+
+
+@pytest.mark.parametrize("r,load", [(3, 0.75), (4, 0.83), (3, 0.9), (2, 0.45)])
+def test_subround_listing_equals_peeling_the_key_hypergraph_with_subtables(r, load):
+    # The paper's GPU process (Section 5, Appendix B): subround (i, j) lists the
+    # pure cells of subtable j.  On the key -> cell hypergraph (cells split into
+    # the same subtables) that is peeling with subtables at k = 2: subround s
+    # lists exactly the edges that subround removes.  The listed set is the
+    # round-synchronous one (the 2-core does not depend on the order), and what
+    # is left is the same table.
+    N = (1 << 14) + 5
+    m = int(load * N)
+    keys, t = _table(N, r, m, seed=40 + r)
+    cells, _ = native.iblt_cells_of(N, r, t.seed, keys)
+    peel = native.peel_subrounds(N, cells.astype(np.uint32), 2)
+    sub_t = t.copy()
+    res = native.iblt_list_subrounds(sub_t)
+    assert res.status == native.OK and not res.corrupt
+    assert res.rounds == peel.edge_rounds
+    for s, grp in enumerate(res.per_round(), start=1):
+        assert np.array_equal(grp, np.sort(keys[peel.edge_round == s])), s
+    rnd_t = t.copy()
+    rnd = native.iblt_list_rounds(rnd_t)
+    assert np.array_equal(np.sort(res.keys), np.sort(rnd.keys))
+    assert np.array_equal(sub_t.count, rnd_t.count)
+    assert np.array_equal(sub_t.key_sum, rnd_t.key_sum)
+    assert np.array_equal(sub_t.hash_sum, rnd_t.hash_sum)
+
+
+def test_subround_listing_limits_and_corrupt_cell():
+    keys, t = _table(4096, 3, 2800, seed=61)
+    full = native.iblt_list_subrounds(t.copy())
+    # a round limit stops before the first subround past it that would list a key
+    cut = native.iblt_list_subrounds(t.copy(), max_rounds=4)
+    assert cut.status == native.EROUNDS and cut.rounds <= 4
+    assert np.array_equal(cut.K, full.K[: cut.rounds])
+    # an output capacity stops before the subround that would overflow it
+    cap = int(full.K[:3].sum()) + 1
+    small = native.iblt_list_subrounds(t.copy(), out_cap=cap)
+    assert small.status == native.ENOSPC and small.keys.size <= cap
+    assert np.array_equal(small.keys, full.keys[: small.keys.size])
+    # a count-1 cell with a wrong checksum is not pure and is reported
+    bad = t.copy()
+    c = int(np.flatnonzero(bad.count == 1)[0])
+    bad.hash_sum[c] ^= np.uint64(1)
+    res = native.iblt_list_subrounds(bad)
+    assert res.corrupt
