@@ -215,6 +215,26 @@ peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_key
                       uint64_t out_cap, uint64_t *round_stats, uint32_t max_rounds,
                       uint64_t *summary, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Listing with subtables (Section 5, "Implementation Details"; Appendix B):
+ * the process the paper's GPU code runs.  Every round is r subrounds;
+ * subround (i, j) lists the key of each cell of subtable j that is pure at the
+ * start of the subround (a key has one cell per subtable, so it is listed
+ * once) and deletes those keys from their r cells.  Subrounds are numbered
+ * s = (i-1) r + j from 1, an empty subround keeping its number; the run ends
+ * when no subtable has a pure cell.  It lists the same keys as iblt_list and
+ * leaves the same table.
+ *
+ * Arguments, outputs and errors are those of iblt_list, with "round" read as
+ * "subround": out_keys is grouped by subround, round_stats[s-1] = keys listed
+ * in subround s (0 for an empty one), max_rounds bounds the subrounds and
+ * summary[1] is the last subround that listed a key.  The workspace is
+ * iblt_list_workspace(desc).
+ */
+peel_status iblt_list_subtables(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
+                                uint64_t out_cap, uint64_t *round_stats, uint32_t max_rounds,
+                                uint64_t *summary, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched listing (many independent tables in one launch).                   */
 /*

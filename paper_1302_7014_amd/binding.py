@@ -28,7 +28,7 @@ FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT = 0x1, 0x2, 
 # Every symbol include/peel.h declares.
 EXPORTS = ("peel_strerror", "peel_abi_version", "hg_build_workspace", "hg_build",
            "peel_kcore_workspace", "peel_kcore", "peel_kcore_subtables", "iblt_insert",
-           "iblt_list_workspace", "iblt_list",
+           "iblt_list_workspace", "iblt_list", "iblt_list_subtables",
            "iblt_list_batched_workspace", "iblt_list_batched")
 
 _lib = None
@@ -65,11 +65,12 @@ def lib() -> C.CDLL:
         L.iblt_list_workspace.argtypes = [C.POINTER(IbltDesc)]
         L.iblt_list_workspace.restype = sz
         L.iblt_list.argtypes = [C.POINTER(IbltDesc), P, P, u64, P, u32, P, P, sz, P]
+        L.iblt_list_subtables.argtypes = L.iblt_list.argtypes
         L.iblt_list_batched_workspace.argtypes = [u32, u64]
         L.iblt_list_batched_workspace.restype = sz
         L.iblt_list_batched.argtypes = [P, u32, u64, u32, C.POINTER(BatchSchedule), P, sz, P]
         for f in ("hg_build", "peel_kcore", "peel_kcore_subtables", "iblt_insert", "iblt_list",
-                  "iblt_list_batched"):
+                  "iblt_list_subtables", "iblt_list_batched"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -198,8 +199,9 @@ def iblt_list_workspace(desc: IbltDesc) -> int:
 
 def iblt_list(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = None,
               max_rounds: int = 4096, out: ListOut | None = None, ws: torch.Tensor | None = None,
-              stream=None) -> ListOut:
-    """Round-synchronous listing; consumes ``cells`` in place."""
+              stream=None, subtables: bool = False) -> ListOut:
+    """Round-synchronous listing; consumes ``cells`` in place.  ``subtables=True``
+    calls iblt_list_subtables: rounds are then subrounds."""
     dev = cells.device
     if out is None:
         cap = desc.ncells if out_cap is None else out_cap
@@ -208,9 +210,10 @@ def iblt_list(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = None,
     cap = out.keys.numel() if out_cap is None else out_cap
     if ws is None:
         ws = workspace(iblt_list_workspace(desc), dev)
-    _check(lib().iblt_list(C.byref(desc), _ptr(cells), _ptr(out.keys), cap, _ptr(out.round_stats),
-                           max_rounds, _ptr(out.summary), _ptr(ws), ws.numel(), _stream(stream)),
-           "iblt_list")
+    fn = lib().iblt_list_subtables if subtables else lib().iblt_list
+    _check(fn(C.byref(desc), _ptr(cells), _ptr(out.keys), cap, _ptr(out.round_stats),
+              max_rounds, _ptr(out.summary), _ptr(ws), ws.numel(), _stream(stream)),
+           "iblt_list_subtables" if subtables else "iblt_list")
     return out
 
 

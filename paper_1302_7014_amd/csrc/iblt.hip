@@ -177,6 +177,8 @@ struct ListCtrl {
   unsigned long long count_sum;  // sum of all counts at the start (two's complement)
   uint32_t ovf_own[2];           // overflow keys found by detect for round u: [u & 1]
   uint32_t ovf_cand[2];          // overflow candidates pushed by apply of round u: [u & 1]
+  uint32_t qn[3];                // subtables mode: candidate queue of subround s has qn[s % 3]
+  uint32_t pad2;
   uint64_t stamp[256];           // wall clock at each barrier generation (diagnostic)
 };
 
@@ -347,6 +349,217 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
   }
   if (slot == 0 && tid == 0) {
     ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
+    ctrl->listed = listed;
+    ctrl->team_size = T;
+  }
+}
+
+// ===========================================================================
+// Listing with subtables (Section 5, "Implementation Details"; Appendix B):
+// the paper's GPU process.  Each round is r subrounds; subround s = (i-1) r + j
+// + 1 lists the key of every cell of subtable j that is pure at its start and
+// deletes those keys from their r cells.  A key has one cell per subtable, so
+// it is listed once without any ownership test.
+//
+// Candidates: in round 1 every cell of subtable j is examined (a dense pass);
+// afterwards only cells that went 2 -> 1 are.  They wait in a queue shared by
+// the team (two buffers of ncells entries; each cell enters it at most once,
+// since counts only fall) until their subtable's subround; a push into a
+// subtable whose round-1 pass is still to come is dropped, that pass covers it.
+// The run ends once round 1 is over and the queue is empty.
+
+constexpr int kLQ = 4096;  // workgroup-local push buffer (flushed to the queue)
+
+template <int R>
+__global__ void __launch_bounds__(kLT) k_list_sub(ListArgs a) {
+  __shared__ uint32_t s_own, s_bad, s_lq, s_qbase;
+  __shared__ unsigned long long s_sum;
+  __shared__ uint32_t lq[kLQ];
+
+  ListCtrl *ctrl = a.ctrl;
+  uint32_t slot, T;
+  if (!team_join(&ctrl->team, a.quiet, a.limit, &slot, &T)) return;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t gtid = (uint64_t)slot * kLT + tid;
+  const uint64_t gsize = (uint64_t)T * kLT;
+  const uint32_t cb = a.cb;
+  const uint32_t N = a.ncells;
+  uint64_t *myKeys = a.skeys + (uint64_t)slot * cb;
+  uint32_t *myOwn = a.scells + (uint64_t)slot * cb;
+  uint32_t *queue[2] = {a.ocand, a.ocand + N};
+
+  auto stage = [&](uint64_t x, uint32_t c, uint32_t parity) {
+    const uint32_t pos = atomicAdd(&s_own, 1u);
+    if (pos < cb) {
+      myKeys[pos] = x;
+      myOwn[pos] = c;
+    } else {
+      const uint32_t q = atomicAdd(&ctrl->ovf_own[parity], 1u);
+      a.okeys[q] = x;
+      a.ocells[q] = c;
+    }
+  };
+  auto flush = [&](uint32_t *nxt, uint32_t *ncount) {
+    __syncthreads();
+    const uint32_t nq = s_lq < (uint32_t)kLQ ? s_lq : (uint32_t)kLQ;
+    if (tid == 0) s_qbase = nq ? atomicAdd(ncount, nq) : 0u;
+    __syncthreads();
+    for (uint32_t i = tid; i < nq; i += kLT) nxt[s_qbase + i] = lq[i];
+  };
+
+  if (slot == 0)
+    for (uint32_t i = tid; i < a.max_rounds; i += kLT) a.stats[i] = 0;
+  uint32_t epoch = 0;
+  uint64_t listed = 0;
+  uint32_t last = 0;
+  uint32_t s = 1;
+  bool early = false;  // stopped before round 1 ended
+  for (;; ++s) {
+    const uint32_t j = (s - 1) % R;
+    const bool first = s <= R;
+    const uint32_t par = s & 1u;
+    const uint32_t *cur = queue[s & 1u];
+    uint32_t *nxt = queue[(s + 1) & 1u];
+    uint32_t *ncount = &ctrl->qn[(s + 1) % 3];
+    const uint32_t size = __hip_atomic_load(&ctrl->qn[s % 3], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+      s_own = 0;
+      s_bad = 0;
+      s_sum = 0;
+      s_lq = 0;
+      if (slot == 0) ctrl->qn[(s + 2) % 3] = 0;  // the next subround's push counter
+    }
+    __syncthreads();
+    auto lpush = [&](uint32_t c) {
+      const uint32_t p = atomicAdd(&s_lq, 1u);
+      if (p < (uint32_t)kLQ)
+        lq[p] = c;
+      else
+        nxt[atomicAdd(ncount, 1u)] = c;
+    };
+    // ---- detect ------------------------------------------------------------
+    {
+      uint32_t bad = 0;
+      if (first) {
+        // every cell of subtable j (its counts also feed the table's key count)
+        const uint32_t lo = (uint32_t)a.h.base[j], sz = (uint32_t)a.h.size[j];
+        const uint32_t cr = (sz + T - 1) / T;
+        const uint32_t c0 = lo + (slot * cr < sz ? slot * cr : sz);
+        const uint32_t c1 = lo + ((slot + 1) * cr < sz ? (slot + 1) * cr : sz);
+        long long local = 0;
+        for (uint32_t c = c0 + tid; c < c1; c += kLT) {
+          int32_t cnt;
+          uint64_t ks, hs;
+          load_cell(a.cells + c, &cnt, &ks, &hs);
+          local += cnt;
+          if (cnt == 1) {
+            if (hs == check_of(a.h, ks))
+              stage(ks, c, par);
+            else
+              bad = 1;
+          }
+        }
+        atomicAdd(&s_sum, (unsigned long long)local);
+      }
+      for (uint64_t i = gtid; i < size; i += gsize) {
+        const uint32_t c = cur[i];
+        if (subtable_of(a.h, c) != j) {  // waits for its subtable's subround
+          lpush(c);
+          continue;
+        }
+        int32_t cnt;
+        uint64_t ks, hs;
+        load_cell(a.cells + c, &cnt, &ks, &hs);
+        if (cnt == 1) {
+          if (hs == check_of(a.h, ks))
+            stage(ks, c, par);
+          else
+            bad = 1;
+        }
+      }
+      if (bad) s_bad = 1;
+    }
+    flush(nxt, ncount);
+    __syncthreads();
+    if (tid == 0) {
+      // Each key listed so far left one cell of subtable j, so the counts of
+      // subtable j now plus those keys are its counts at the start.
+      if (first) {
+        const unsigned long long add = s_sum + (slot == 0 ? listed : 0ull);
+        if (add) atomicAdd(&ctrl->count_sum, add);
+      }
+      if (s_bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
+    }
+    const uint32_t staged = s_own < cb ? s_own : cb;
+    uint64_t total, prefix;
+    if (!sum_barrier(&ctrl->bar, T, slot, staged, &epoch, a.limit, &total, ctrl->stamp, &prefix))
+      return;
+    const uint32_t ovf =
+        __hip_atomic_load(&ctrl->ovf_own[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t K = total + ovf;
+    if (K == 0) {
+      // nothing listed: the queue holds only waiting cells
+      if (s >= R && __hip_atomic_load(ncount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        break;
+      continue;
+    }
+    if (s > a.max_rounds) {
+      if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_EROUNDS);
+      early = s < R;
+      break;
+    }
+    if (listed + K > a.out_cap) {
+      if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_ENOSPC);
+      early = s < R;
+      break;
+    }
+    // ---- outputs of subround s, then apply -----------------------------------
+    for (uint32_t i = tid; i < staged; i += kLT) a.out[listed + prefix + i] = myKeys[i];
+    for (uint64_t q = gtid; q < ovf; q += gsize) a.out[listed + total + q] = a.okeys[q];
+    if (slot == 0 && tid == 0) a.stats[s - 1] = K;
+    if (tid == 0) s_lq = 0;
+    __syncthreads();
+    auto push = [&](uint32_t c) {
+      // a subtable whose round-1 pass is still to come will see c anyway
+      if (first && subtable_of(a.h, c) > j) return;
+      lpush(c);
+    };
+    for (uint32_t i = tid; i < staged; i += kLT) delete_key<R>(a.h, a.cells, myKeys[i], myOwn[i], push);
+    for (uint64_t q = gtid; q < ovf; q += gsize) delete_key<R>(a.h, a.cells, a.okeys[q], a.ocells[q], push);
+    flush(nxt, ncount);
+    uint64_t dummy;
+    if (!sum_barrier(&ctrl->bar, T, slot, 0, &epoch, a.limit, &dummy, ctrl->stamp)) return;
+    listed += K;
+    last = s;
+    if (slot == 0 && tid == 0) ctrl->ovf_own[par] = 0;  // consumed
+    if (s >= R && __hip_atomic_load(ncount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      break;
+  }
+  if (early) {
+    // stopped inside round 1: the subtables not yet passed over are summed now,
+    // each of their counts plus one per key listed so far
+    for (uint32_t jj = (s - 1) % R + 1; jj < R; ++jj) {
+      const uint32_t lo = (uint32_t)a.h.base[jj], sz = (uint32_t)a.h.size[jj];
+      long long local = 0;
+      for (uint64_t c = gtid; c < sz; c += gsize) {
+        int32_t cnt;
+        uint64_t ks, hs;
+        load_cell(a.cells + lo + c, &cnt, &ks, &hs);
+        local += cnt;
+      }
+      if (tid == 0) s_sum = 0;
+      __syncthreads();
+      atomicAdd(&s_sum, (unsigned long long)local);
+      __syncthreads();
+      if (tid == 0) {
+        const unsigned long long add = s_sum + (slot == 0 ? listed : 0ull);
+        if (add) atomicAdd(&ctrl->count_sum, add);
+      }
+    }
+  }
+  if (slot == 0 && tid == 0) {
+    ctrl->rounds = last;
     ctrl->listed = listed;
     ctrl->team_size = T;
   }
@@ -707,9 +920,12 @@ peel_status launch_insert(const Hash &h, iblt_cell *cells, const uint64_t *keys,
 }
 
 template <int R>
-peel_status launch_list(ListArgs &a, hipStream_t s) {
+peel_status launch_list(ListArgs &a, hipStream_t s, bool subtables) {
   if (device_info().debug) std::fprintf(stderr, "[peel] list grid %u\n", a.grid);
-  hipLaunchKernelGGL(k_list_persistent<R>, dim3(a.grid), dim3(kLT), 0, s, a);
+  if (subtables)
+    hipLaunchKernelGGL(k_list_sub<R>, dim3(a.grid), dim3(kLT), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_list_persistent<R>, dim3(a.grid), dim3(kLT), 0, s, a);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }
@@ -751,9 +967,12 @@ extern "C" size_t iblt_list_workspace(const iblt_desc *desc) {
   return desc_ok(desc) ? list_layout(desc->ncells, desc->workgroups).total : 0;
 }
 
-extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
-                                 uint64_t out_cap, uint64_t *round_stats, uint32_t max_rounds,
-                                 uint64_t *summary, void *ws, size_t ws_bytes, void *stream) {
+namespace peel {
+namespace {
+
+peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
+                     uint64_t out_cap, uint64_t *round_stats, uint32_t max_rounds,
+                     uint64_t *summary, void *ws, size_t ws_bytes, void *stream, bool subtables) {
   if (!desc_ok(desc) || !cells || (out_cap && !out_keys) || !round_stats || !summary || !ws ||
       max_rounds == 0)
     return PEEL_EINVAL;
@@ -791,18 +1010,37 @@ extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64
   PEEL_HIP_TRY(hipGetLastError());
   peel_status st;
   switch (desc->r) {
-    case 2: st = launch_list<2>(a, s); break;
-    case 3: st = launch_list<3>(a, s); break;
-    case 4: st = launch_list<4>(a, s); break;
-    case 5: st = launch_list<5>(a, s); break;
-    case 6: st = launch_list<6>(a, s); break;
-    case 7: st = launch_list<7>(a, s); break;
-    default: st = launch_list<8>(a, s); break;
+    case 2: st = launch_list<2>(a, s, subtables); break;
+    case 3: st = launch_list<3>(a, s, subtables); break;
+    case 4: st = launch_list<4>(a, s, subtables); break;
+    case 5: st = launch_list<5>(a, s, subtables); break;
+    case 6: st = launch_list<6>(a, s, subtables); break;
+    case 7: st = launch_list<7>(a, s, subtables); break;
+    default: st = launch_list<8>(a, s, subtables); break;
   }
   if (st) return st;
   hipLaunchKernelGGL(k_list_finish, dim3(1), dim3(64), 0, s, a.ctrl, desc->r, summary);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
+}
+
+}  // namespace
+}  // namespace peel
+
+extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
+                                 uint64_t out_cap, uint64_t *round_stats, uint32_t max_rounds,
+                                 uint64_t *summary, void *ws, size_t ws_bytes, void *stream) {
+  return list_run(desc, cells, out_keys, out_cap, round_stats, max_rounds, summary, ws, ws_bytes,
+                  stream, false);
+}
+
+extern "C" peel_status iblt_list_subtables(const iblt_desc *desc, iblt_cell *cells,
+                                           uint64_t *out_keys, uint64_t out_cap,
+                                           uint64_t *round_stats, uint32_t max_rounds,
+                                           uint64_t *summary, void *ws, size_t ws_bytes,
+                                           void *stream) {
+  return list_run(desc, cells, out_keys, out_cap, round_stats, max_rounds, summary, ws, ws_bytes,
+                  stream, true);
 }
 
 extern "C" size_t iblt_list_batched_workspace(uint32_t ntables, uint64_t max_cells) {
