@@ -421,7 +421,7 @@ def main():
         extra["serve"] = bench_serve(configs.served_main(), 1000, args.serve_requests, 500)
     if args.sweep:
         sw = []
-        for c in configs.SWEEP_C:
+        for c in configs.SWEEP_C + configs.NEAR_C:
             s2 = configs.kcore_sweep(c)
             r2 = bench_kcore(s2, max(3, args.steps // 4), 1)
             sw.append({"workload": s2.name, "m": s2.m, "rounds": r2["rounds"],

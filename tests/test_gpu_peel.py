@@ -171,6 +171,18 @@ def test_full_size_sweep_r4_n16M(c):
                                         res["edge_rounds"]) == []
 
 
+@pytest.mark.parametrize("c", configs.NEAR_C)
+def test_full_size_near_threshold(c):
+    # just below c*_{2,4}: tens to hundreds of rounds (Theorem 5), bit for bit
+    need_gpu()
+    spec = configs.kcore_sweep(c)
+    e = spec.edges(1)
+    say(spec.name, "near threshold")
+    res = gpu_peel(spec.n, e, spec.k)
+    assert res["flags"] == 0
+    _check_against_oracle(spec.n, e, spec.k, res)
+
+
 @pytest.mark.parametrize("c,mode", [(0.70, "dense"), (0.85, "auto")])
 def test_full_size_forced_round_kind(c, mode, monkeypatch):
     # every round of one kind at full size: both kinds give the oracle's answer

@@ -1,6 +1,8 @@
 """Pins for the oracle's threshold and recursion code (paper, Sections 2-4, Appendix B)."""
 import math
 
+import numpy as np
+
 import pytest
 
 from oracle import theory
@@ -98,3 +100,25 @@ def test_predicted_rounds_bracket_table1(golden):
     # Table 1, c=0.7: the measured mean is 12.5-13 rounds; the recursion predicts 13 at n=10^6.
     assert theory.predicted_rounds(0.70, 2, 4, 10 ** 6) == 13
     assert theory.predicted_rounds(0.70, 2, 4, 10 ** 4) in (12, 13)
+
+
+def test_rounds_near_threshold_grow_like_inverse_sqrt_distance():
+    # Theorem 5: below the threshold, Theta(sqrt(1/nu)) + O(log log n) rounds with
+    # nu = c* - c.  In the recursion's prediction, a 4x smaller nu doubles the
+    # rounds once the sqrt term dominates.
+    cs = theory.cstar(2, 4)[0]
+    rounds = [theory.predicted_rounds(cs - nu, 2, 4, 1 << 24) for nu in (4e-3, 1e-3, 2.5e-4, 6.25e-5)]
+    for a, b in zip(rounds, rounds[1:]):
+        assert 1.8 <= b / a <= 2.2, rounds
+
+
+def test_measured_rounds_near_threshold_follow_the_recursion():
+    # the round-synchronous simulator just below c*_{2,4}, n = 2^20, 4 seeds:
+    # the mean round count lands on the recursion's first t with lambda_t n < 1/2
+    from oracle import native
+    from workloads import gen
+    n = 1 << 20
+    for c, tol in ((0.76, 1.5), (0.77, 0.15 * theory.predicted_rounds(0.77, 2, 4, n))):
+        rs = [native.peel_rounds(n, gen.partitioned_edges(n, int(c * n), 4, 50 + s), 2).rounds
+              for s in range(4)]
+        assert abs(np.mean(rs) - theory.predicted_rounds(c, 2, 4, n)) <= tol, (c, rs)

@@ -3,7 +3,8 @@
 Hypergraph workloads (peeling to the k-core, Sections 1 and 3):
   * ``kcore_r3_k2_n64K``: r=3, k=2, n=2^16, m=round(0.70 n), partitioned edges.
   * ``kcore_r4_k2_n16M_c{c}``: r=4, k=2, n=2^24, c in {0.60, 0.70, 0.75, 0.80, 0.85}
-    (c*_{2,4} ~ 0.7723 lies between 0.75 and 0.80), partitioned edges.
+    (c*_{2,4} ~ 0.7723 lies between 0.75 and 0.80), and just below the threshold
+    c in {0.76, 0.77, 0.772}; partitioned edges.
   * ``kcore_r3_k3_n4M_{lo,hi}``: r=3, k=3, n=2^22 at 0.9 and 1.1 c*_{3,3}.
 
 IBLT workloads (Section 5):
@@ -75,11 +76,14 @@ def kcore_small() -> HypergraphSpec:
 
 
 SWEEP_C = (0.60, 0.70, 0.75, 0.80, 0.85)
+# just below c*_{2,4} ~ 0.77228, where the rounds grow like 1/sqrt(c* - c) (Theorem 5)
+NEAR_C = (0.76, 0.77, 0.772)
 
 
 def kcore_sweep(c: float) -> HypergraphSpec:
     n = 1 << 24
-    return HypergraphSpec(f"kcore_r4_k2_n16M_c{c:.2f}", n, int(round(c * n)), 4, 2)
+    tag = f"{c:.2f}" if round(c, 2) == c else f"{c:.3f}"
+    return HypergraphSpec(f"kcore_r4_k2_n16M_c{tag}", n, int(round(c * n)), 4, 2)
 
 
 def kcore_k3(which: str) -> HypergraphSpec:
