@@ -48,9 +48,11 @@ def lib():
         L.orc_iblt_update.argtypes = [u64, u32, u64, P, P, P, P, u64, i32]
         L.orc_iblt_list_rounds.argtypes = [u64, u32, u64, P, P, P, P, u64, P, u32, P, P, P]
         L.orc_iblt_list_subrounds.argtypes = L.orc_iblt_list_rounds.argtypes
+        L.orc_iblt_list_signed.argtypes = [u64, u32, u64, P, P, P, P, P, u64, P, u32, P, P, P]
         L.orc_iblt_list_seq.argtypes = [u64, u32, u64, P, P, P, P, u64, P]
         for f in ("orc_peel_rounds", "orc_peel_subrounds", "orc_peel_queue", "orc_core_brute", "orc_iblt_cells_of",
                   "orc_iblt_update", "orc_iblt_list_rounds", "orc_iblt_list_subrounds",
+                  "orc_iblt_list_signed",
                   "orc_iblt_list_seq"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -248,6 +250,46 @@ def iblt_list_subrounds(t: IbltTable, max_rounds: int = 1 << 20,
     if st not in (OK, EROUNDS, ENOSPC):
         raise RuntimeError(f"orc_iblt_list_subrounds failed: {st}")
     return ListResult(st, out[: nl.value].copy(), K[: R.value].copy(), R.value, bool(bad.value))
+
+
+@dataclass
+class SignedListResult:
+    status: int
+    keys: np.ndarray     # uint64[n_listed], grouped by round, ascending within a round
+    signs: np.ndarray    # int8[n_listed]: +1 inserted, -1 deleted
+    K: np.ndarray        # uint64[rounds]
+    rounds: int
+    nonempty: int        # cells left non-zero
+
+    def per_round(self):
+        out, off = [], 0
+        for kk in self.K.tolist():
+            out.append((self.keys[off: off + kk], self.signs[off: off + kk]))
+            off += kk
+        return out
+
+
+def iblt_list_signed(t: IbltTable, max_rounds: int = 1 << 20,
+                     out_cap: int | None = None) -> SignedListResult:
+    """Round-synchronous listing of a table holding deletions too (Section 5); pure =
+    count +-1 with a matching checksum; consumes ``t``."""
+    cap = t.ncells if out_cap is None else out_cap
+    out = np.zeros(max(cap, 1), np.uint64)
+    sg = np.zeros(max(cap, 1), np.int8)
+    kcap = min(max_rounds, t.ncells) + 1
+    K = np.zeros(kcap, np.uint64)
+    nl = C.c_uint64(0)
+    R = C.c_uint32(0)
+    ne = C.c_uint64(0)
+    st = lib().orc_iblt_list_signed(t.ncells, t.r, t.seed, _p(t.count), _p(t.key_sum),
+                                    _p(t.hash_sum), _p(out), _p(sg), cap, _p(K),
+                                    min(max_rounds, kcap - 1), C.byref(nl), C.byref(R),
+                                    C.byref(ne))
+    if st not in (OK, EROUNDS, ENOSPC):
+        raise RuntimeError(f"orc_iblt_list_signed failed: {st}")
+    n = nl.value
+    return SignedListResult(st, out[:n].copy(), sg[:n].copy(), K[: R.value].copy(), R.value,
+                            ne.value)
 
 
 def iblt_list_seq(t: IbltTable) -> np.ndarray:

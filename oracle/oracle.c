@@ -622,3 +622,77 @@ int orc_iblt_list_subrounds(uint64_t ncells, uint32_t r, uint64_t seed,
     *corrupt_out = corrupt;
     return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Listing a table that holds deletions too (Section 5, "Motivation": the    */
+/* count field goes down on a deletion, and the table can hold the          */
+/* difference of two sets).  A cell is pure when its count is +1 or -1 and    */
+/* its checksum field is C(key_sum): it holds that one key, inserted (+1) or  */
+/* deleted (-1) once more than the other way.  Round t takes the pure cells   */
+/* at its start, lists each key once with its sign, and takes every listed    */
+/* key back out of its r cells (count -= sign, XOR the fields).  A count of   */
+/* +-1 with a wrong checksum is ordinary here (a cell holding several keys). */
+/* signs[i] is the sign of out_keys[i]; *nonempty_out = cells left non-zero.  */
+
+typedef struct { uint64_t key; int32_t sign; } orc_signed_key;
+
+static int orc_cmp_signed(const void *a, const void *b)
+{
+    uint64_t x = ((const orc_signed_key *)a)->key, y = ((const orc_signed_key *)b)->key;
+    return x < y ? -1 : x > y ? 1 : 0;
+}
+
+int orc_iblt_list_signed(uint64_t ncells, uint32_t r, uint64_t seed,
+                         int32_t *count, uint64_t *key_sum, uint64_t *hash_sum,
+                         uint64_t *out_keys, int8_t *signs, uint64_t out_cap,
+                         uint64_t *K, uint32_t max_rounds,
+                         uint64_t *n_listed_out, uint32_t *rounds_out,
+                         uint64_t *nonempty_out)
+{
+    orc_iblt t;
+    uint64_t n_listed = 0, c, ne = 0;
+    orc_signed_key *got;
+    uint32_t round;
+    int rc = orc_iblt_setup(&t, ncells, r, seed);
+    if (rc) return rc;
+    got = (orc_signed_key *)malloc((size_t)ncells * sizeof(orc_signed_key));
+    if (!got) return ORC_ENOMEM;
+    *rounds_out = 0;
+    for (round = 1;; round++) {
+        uint64_t np = 0, nk = 0, i;
+        for (c = 0; c < ncells; c++) {
+            if (count[c] != 1 && count[c] != -1) continue;
+            if (hash_sum[c] != orc_iblt_check(&t, key_sum[c])) continue;
+            got[np].key = key_sum[c];
+            got[np].sign = count[c];
+            np++;
+        }
+        if (np == 0) break;
+        if (round > max_rounds) { rc = ORC_EROUNDS; break; }
+        qsort(got, np, sizeof(orc_signed_key), orc_cmp_signed);
+        for (i = 0; i < np; i++)
+            if (i == 0 || got[i].key != got[i - 1].key) got[nk++] = got[i];
+        if (n_listed + nk > out_cap) { rc = ORC_ENOSPC; break; }
+        for (i = 0; i < nk; i++) {
+            uint64_t x = got[i].key, h = orc_iblt_check(&t, x);
+            uint32_t j;
+            out_keys[n_listed + i] = x;
+            signs[n_listed + i] = (int8_t)got[i].sign;
+            for (j = 0; j < r; j++) {
+                uint64_t cc = orc_iblt_cell(&t, j, x);
+                count[cc] -= got[i].sign;
+                key_sum[cc] ^= x;
+                hash_sum[cc] ^= h;
+            }
+        }
+        K[round - 1] = nk;
+        n_listed += nk;
+        *rounds_out = round;
+    }
+    for (c = 0; c < ncells; c++)
+        if (count[c] != 0 || key_sum[c] != 0 || hash_sum[c] != 0) ne++;
+    free(got);
+    *n_listed_out = n_listed;
+    *nonempty_out = ne;
+    return rc;
+}

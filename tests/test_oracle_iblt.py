@@ -157,3 +157,47 @@ def test_subround_listing_limits_and_corrupt_cell():
     bad.hash_sum[c] ^= np.uint64(1)
     res = native.iblt_list_subrounds(bad)
     assert res.corrupt
+
+
+@pytest.mark.parametrize("r", [3, 4])
+def test_signed_listing_recovers_the_set_difference(r):
+    # Section 5: insert A, delete B; below threshold the listing recovers
+    # A \ B with sign +1 and B \ A with sign -1, exactly, and empties the table.
+    N = (1 << 14) + 3
+    pool = gen.distinct_keys(int(0.95 * N), 70 + r)
+    a = pool[: int(0.65 * N)]
+    b = pool[int(0.35 * N):]  # shares 0.3 N keys with a
+    seed = gen.table_seed(70 + r)
+    t = native.iblt_insert(N, r, seed, a)
+    native.iblt_update(t, b, sign=-1)
+    res = native.iblt_list_signed(t.copy())
+    assert res.status == native.OK and res.nonempty == 0
+    plus = np.sort(res.keys[res.signs == 1])
+    minus = np.sort(res.keys[res.signs == -1])
+    assert np.array_equal(plus, np.sort(np.setdiff1d(a, b)))
+    assert np.array_equal(minus, np.sort(np.setdiff1d(b, a)))
+    assert set(res.signs.tolist()) <= {1, -1}
+
+
+def test_signed_listing_rounds_equal_plain_listing_of_the_difference():
+    # Counts and XORs are linear: the table of (insert A, delete B) has the pure
+    # cells of the table of A xor B inserted, up to checksum collisions, so the
+    # round-by-round key sets are those of the plain listing of A xor B; above
+    # the threshold both stop at the same core.
+    for r, frac in [(3, 0.7), (3, 0.95), (4, 0.9)]:
+        N = 1 << 14
+        pool = gen.distinct_keys(int(1.6 * frac * N), 80 + r)
+        half = pool.size // 2
+        a, b = pool[: half + half // 2], pool[half // 2:]
+        diff = np.setxor1d(a, b)
+        seed = gen.table_seed(80 + r)
+        t = native.iblt_insert(N, r, seed, a)
+        native.iblt_update(t, b, sign=-1)
+        res = native.iblt_list_signed(t)
+        plain = native.iblt_list_rounds(native.iblt_insert(N, r, seed, diff))
+        assert res.rounds == plain.rounds
+        assert np.array_equal(res.K, plain.K)
+        for (ks, sg), want in zip(res.per_round(), plain.per_round()):
+            assert np.array_equal(ks, want)
+            assert np.array_equal(sg, np.where(np.isin(ks, a), 1, -1).astype(np.int8))
+        assert res.nonempty == int(((t.count != 0) | (t.key_sum != 0) | (t.hash_sum != 0)).sum())
