@@ -210,6 +210,40 @@ def bench_iblt(spec, reps):
     }
 
 
+def bench_signed(reps):
+    """Set difference (Section 5): insert A, delete B, list the signed table.
+    2^24 cells, r = 3, |A| = |B| = 8.05 M keys, |A xor B| = 7.05 M (load 0.42)."""
+    N, r = 1 << 24, 3
+    na = nb = int(0.48 * N)
+    no = int(0.27 * N)
+    pool = torch.from_numpy(gen.distinct_keys(na + nb - no, 901).view(np.int64)).cuda()
+    a, b = pool[:na], pool[na - no:]
+    d = pk.iblt_desc(N, r, gen.table_seed(901))
+    cells = pk.iblt_table(N, "cuda")
+    out = pk.SignedListOut(torch.empty(N, dtype=torch.int64, device="cuda"),
+                           torch.empty(N, dtype=torch.int8, device="cuda"),
+                           torch.empty(4096, dtype=torch.int64, device="cuda"),
+                           torch.empty(8, dtype=torch.int64, device="cuda"))
+    ws = pk.workspace(pk.iblt_list_workspace(d), "cuda")
+    tu, tl = Timer(), Timer()
+    for _ in range(reps + 2):
+        cells.zero_()
+        with tu:
+            pk.iblt_insert(d, cells, a)
+            pk.iblt_delete(d, cells, b)
+        with tl:
+            pk.iblt_list_signed(d, cells, max_rounds=4096, out=out, ws=ws)
+        tl.collect()
+        tu.collect()
+    s = out.summary.cpu().numpy()
+    lst = float(np.median(tl.ms[2:]))
+    upd = float(np.median(tu.ms[2:]))
+    return {"workload": "iblt_signed_r3_N16M_diff7M", "cells": N, "inserted": na, "deleted": nb,
+            "difference": na + nb - 2 * no, "listed": int(s[0]), "rounds": int(s[1]),
+            "cells_left": int(s[2]), "update_ms": upd, "list_ms": lst,
+            "list_keys_per_s": int(s[0]) / (lst * 1e-3)}
+
+
 def bench_batched(spec, reps):
     """One launch for every table (block-per-table schedule) vs one iblt_list per table."""
     draw = spec.draw(1)
@@ -415,6 +449,7 @@ def main():
         log("IBLT 2^24 cells")
         extra["iblt"] = [bench_iblt(configs.iblt_main(), 5),
                          bench_iblt(configs.iblt_paper(3, 0.75), 5)]
+        extra["iblt_signed"] = bench_signed(5)
     torch.cuda.empty_cache()
     if not args.no_serve:
         log("served decoding")

@@ -190,6 +190,17 @@ peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, const uint64_t 
                         uint64_t nkeys, void *stream);
 
 /*
+ * Delete keys: for each key x and each subtable j, count -= 1, key_sum ^= x,
+ * hash_sum ^= C(x) in x's cell of subtable j (Section 5, "Motivation": the
+ * same update with the count going down).  A key deleted without having been
+ * inserted stays in the table with count -1 in its cells: inserting a set A
+ * and deleting a set B leaves the table of their difference.  Arguments as
+ * for iblt_insert.
+ */
+peel_status iblt_delete(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
+                        uint64_t nkeys, void *stream);
+
+/*
  * List the table by round-synchronous pure-cell peeling, consuming `cells`
  * in place.  Round t takes K_t = the keys of the cells that are pure at the
  * start of the round (each key once, however many of its cells are pure);
@@ -214,6 +225,27 @@ size_t iblt_list_workspace(const iblt_desc *desc);
 peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
                       uint64_t out_cap, uint64_t *round_stats, uint32_t max_rounds,
                       uint64_t *summary, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Signed listing, for tables that hold deletions too (Section 5): a cell is
+ * pure when its count is +1 or -1 and hash_sum == C(key_sum); each round
+ * lists the keys of the cells pure at its start, each once with its sign (the
+ * pure cell's count: +1 for a key inserted, -1 for a key deleted), and takes
+ * every listed key back out of its r cells (count -= sign, XOR the fields).
+ * Listing the table of "insert A, delete B" gives A \ B with sign +1 and
+ * B \ A with sign -1 once the difference is below the threshold.
+ *
+ *   out_signs   (device, out) out_cap int8: out_signs[i] is the sign of
+ *               out_keys[i].
+ * Other arguments and limits as for iblt_list, except: a count of +-1 with a
+ * wrong checksum is an ordinary cell here (never PEEL_FLAG_ECORRUPT), and
+ * summary[2] is the number of cells left non-zero (0 means the difference
+ * was listed whole).
+ */
+peel_status iblt_list_signed(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
+                             int8_t *out_signs, uint64_t out_cap, uint64_t *round_stats,
+                             uint32_t max_rounds, uint64_t *summary, void *ws, size_t ws_bytes,
+                             void *stream);
 
 /*
  * Listing with subtables (Section 5, "Implementation Details"; Appendix B):

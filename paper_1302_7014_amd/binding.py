@@ -28,7 +28,8 @@ FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT = 0x1, 0x2, 
 # Every symbol include/peel.h declares.
 EXPORTS = ("peel_strerror", "peel_abi_version", "hg_build_workspace", "hg_build",
            "peel_kcore_workspace", "peel_kcore", "peel_kcore_subtables", "iblt_insert",
-           "iblt_list_workspace", "iblt_list", "iblt_list_subtables",
+           "iblt_delete", "iblt_list_workspace", "iblt_list", "iblt_list_subtables",
+           "iblt_list_signed",
            "iblt_list_batched_workspace", "iblt_list_batched")
 
 _lib = None
@@ -66,11 +67,13 @@ def lib() -> C.CDLL:
         L.iblt_list_workspace.restype = sz
         L.iblt_list.argtypes = [C.POINTER(IbltDesc), P, P, u64, P, u32, P, P, sz, P]
         L.iblt_list_subtables.argtypes = L.iblt_list.argtypes
+        L.iblt_list_signed.argtypes = [C.POINTER(IbltDesc), P, P, P, u64, P, u32, P, P, sz, P]
+        L.iblt_delete.argtypes = L.iblt_insert.argtypes
         L.iblt_list_batched_workspace.argtypes = [u32, u64]
         L.iblt_list_batched_workspace.restype = sz
         L.iblt_list_batched.argtypes = [P, u32, u64, u32, C.POINTER(BatchSchedule), P, sz, P]
-        for f in ("hg_build", "peel_kcore", "peel_kcore_subtables", "iblt_insert", "iblt_list",
-                  "iblt_list_subtables", "iblt_list_batched"):
+        for f in ("hg_build", "peel_kcore", "peel_kcore_subtables", "iblt_insert", "iblt_delete",
+                  "iblt_list", "iblt_list_subtables", "iblt_list_signed", "iblt_list_batched"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -186,6 +189,12 @@ def iblt_insert(desc: IbltDesc, cells: torch.Tensor, keys: torch.Tensor, stream=
                              _stream(stream)), "iblt_insert")
 
 
+def iblt_delete(desc: IbltDesc, cells: torch.Tensor, keys: torch.Tensor, stream=None) -> None:
+    """Delete ``keys`` from ``cells`` (count down, same XORs)."""
+    _check(lib().iblt_delete(C.byref(desc), _ptr(cells), _ptr(keys), keys.numel(),
+                             _stream(stream)), "iblt_delete")
+
+
 @dataclass
 class ListOut:
     keys: torch.Tensor         # int64[out_cap]
@@ -214,6 +223,32 @@ def iblt_list(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = None,
     _check(fn(C.byref(desc), _ptr(cells), _ptr(out.keys), cap, _ptr(out.round_stats),
               max_rounds, _ptr(out.summary), _ptr(ws), ws.numel(), _stream(stream)),
            "iblt_list_subtables" if subtables else "iblt_list")
+    return out
+
+
+@dataclass
+class SignedListOut:
+    keys: torch.Tensor         # int64[out_cap]
+    signs: torch.Tensor        # int8[out_cap]
+    round_stats: torch.Tensor  # int64[max_rounds]
+    summary: torch.Tensor      # int64[8]; [2] = cells left non-zero
+
+
+def iblt_list_signed(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = None,
+                     max_rounds: int = 4096, out: SignedListOut | None = None,
+                     ws: torch.Tensor | None = None, stream=None) -> SignedListOut:
+    """Signed listing of a table that holds deletions too; consumes ``cells``."""
+    dev = cells.device
+    if out is None:
+        cap = desc.ncells if out_cap is None else out_cap
+        out = SignedListOut(_empty(cap, torch.int64, dev), _empty(cap, torch.int8, dev),
+                            _empty(max_rounds, torch.int64, dev), _empty(8, torch.int64, dev))
+    cap = out.keys.numel() if out_cap is None else out_cap
+    if ws is None:
+        ws = workspace(iblt_list_workspace(desc), dev)
+    _check(lib().iblt_list_signed(C.byref(desc), _ptr(cells), _ptr(out.keys), _ptr(out.signs), cap,
+                                  _ptr(out.round_stats), max_rounds, _ptr(out.summary), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "iblt_list_signed")
     return out
 
 

@@ -76,7 +76,8 @@ __device__ inline uint32_t subtable_of(const Hash &h, uint32_t c) {
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ void __launch_bounds__(kBlock)
-    k_insert(Hash h, iblt_cell *cells, const uint64_t *__restrict__ keys, uint64_t nkeys) {
+    k_insert(Hash h, iblt_cell *cells, const uint64_t *__restrict__ keys, uint64_t nkeys,
+             int32_t sign) {
   for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < nkeys;
        i += (uint64_t)gridDim.x * kBlock) {
     const uint64_t x = keys[i];
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       iblt_cell *cell = cells + cell_of(h, j, x);
-      atomicAdd(&cell->count, 1);
+      atomicAdd(&cell->count, sign);
       atomicXor(reinterpret_cast<unsigned long long *>(&cell->key_sum), (unsigned long long)x);
       atomicXor(reinterpret_cast<unsigned long long *>(&cell->hash_sum), (unsigned long long)c);
     }
@@ -112,13 +113,15 @@ __device__ inline void load_cell(const iblt_cell *cell, int32_t *cnt, uint64_t *
 // True when cell c (already read as cnt/ks/hs) is pure and it is the owner of
 // its key: no cell of the key in a lower subtable is a pure cell of that key.
 // Sets *bad for a count-1 cell whose checksum does not match.
-template <int R>
+// SIGNED (tables holding deletions too): a count of -1 is pure as well, and a
+// count of +-1 with a wrong checksum is an ordinary cell holding several keys.
+template <int R, bool SIGNED = false>
 __device__ inline bool owns(const Hash &h, const iblt_cell *cells, uint32_t c, int32_t cnt,
                             uint64_t ks, uint64_t hs, uint32_t *bad) {
-  if (cnt != 1) return false;
+  if (cnt != 1 && !(SIGNED && cnt == -1)) return false;
   const uint64_t hx = check_of(h, ks);
   if (hs != hx) {
-    *bad = 1;
+    if (!SIGNED) *bad = 1;
     return false;
   }
   const uint32_t j = subtable_of(h, c);
@@ -128,16 +131,18 @@ __device__ inline bool owns(const Hash &h, const iblt_cell *cells, uint32_t c, i
     int32_t oc;
     uint64_t ok, oh;
     load_cell(cells + cell_of(h, i, ks), &oc, &ok, &oh);
-    if (oc == 1 && ok == ks && oh == hx) return false;
+    if ((oc == 1 || (SIGNED && oc == -1)) && ok == ks && oh == hx) return false;
   }
   return true;
 }
 
 // Deletes key x from its R cells; the cell it was listed from (c_own) is simply
 // cleared.  Calls push(c) for every cell whose count goes 2 -> 1.
-template <int R, typename Push>
+// SIGNED: x leaves with its sign (count -= sign) and a cell whose count lands on
+// +-1 is pushed (signed counts need not fall monotonically).
+template <int R, bool SIGNED = false, typename Push>
 __device__ inline void delete_key(const Hash &h, iblt_cell *cells, uint64_t x, uint32_t c_own,
-                                  Push push) {
+                                  Push push, int32_t sign = 1) {
   const uint64_t hx = check_of(h, x);
 #pragma unroll
   for (int j = 0; j < R; ++j) {
@@ -147,10 +152,10 @@ __device__ inline void delete_key(const Hash &h, iblt_cell *cells, uint64_t x, u
       clear_cell(cell);
       continue;
     }
-    const int32_t old = atomicSub(&cell->count, 1);
+    const int32_t old = atomicSub(&cell->count, sign);
     atomicXor(reinterpret_cast<unsigned long long *>(&cell->key_sum), (unsigned long long)x);
     atomicXor(reinterpret_cast<unsigned long long *>(&cell->hash_sum), (unsigned long long)hx);
-    if (old == 2) push(c);
+    if (SIGNED ? (old - sign == 1 || old - sign == -1) : old == 2) push(c);
   }
 }
 
@@ -179,6 +184,7 @@ struct ListCtrl {
   uint32_t ovf_cand[2];          // overflow candidates pushed by apply of round u: [u & 1]
   uint32_t qn[3];                // subtables mode: candidate queue of subround s has qn[s % 3]
   uint32_t pad2;
+  unsigned long long nonempty;   // signed listing: cells left non-zero
   uint64_t stamp[256];           // wall clock at each barrier generation (diagnostic)
 };
 
@@ -194,6 +200,8 @@ struct ListArgs {
   uint64_t *okeys;   // ncells overflow keys
   uint32_t *ocells;  // ncells
   uint32_t *ocand;   // 2 * ncells overflow candidates
+  int8_t *signs;     // signed listing: the sign of each listed key
+  uint32_t signed_list;
   ListCtrl *ctrl;
   uint64_t limit;
   uint64_t quiet;
@@ -208,7 +216,13 @@ __global__ void k_list_init(ListCtrl *ctrl) {
   for (uint32_t i = threadIdx.x; i < sizeof(ListCtrl) / 4; i += blockDim.x) w[i] = 0;
 }
 
-template <int R>
+// Claims cell c for this round's listing (signed tables: a cell can be queued
+// twice in a round, since its count can pass +-1 twice); the listing clears it.
+__device__ inline bool claim_cell(iblt_cell *cells, uint32_t c) {
+  return atomicCAS(&cells[c].reserved0, 0u, 1u) == 0u;
+}
+
+template <int R, bool SIGNED = false>
 __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
   __shared__ uint32_t s_own, s_cand, s_bad;
   __shared__ unsigned long long s_sum;
@@ -257,7 +271,8 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
       uint64_t ks, hs;
       load_cell(a.cells + c, &cnt, &ks, &hs);
       local += cnt;
-      if (owns<R>(a.h, a.cells, c, cnt, ks, hs, &bad)) stage(ks, c, 1u);
+      if (owns<R, SIGNED>(a.h, a.cells, c, cnt, ks, hs, &bad) && (!SIGNED || claim_cell(a.cells, c)))
+        stage(ks, c, 1u);
     }
     if (bad) s_bad = 1;
     atomicAdd(&s_sum, (unsigned long long)local);
@@ -279,17 +294,24 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
   for (;; ++t) {
     const uint64_t K = total + ovf;
     if (K == 0) break;
-    if (t > a.max_rounds) {
-      if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_EROUNDS);
-      break;
-    }
-    if (listed + K > a.out_cap) {
-      if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_ENOSPC);
+    if (t > a.max_rounds || listed + K > a.out_cap) {
+      if (slot == 0 && tid == 0)
+        atomicOr(&ctrl->flags, t > a.max_rounds ? PEEL_FLAG_EROUNDS : PEEL_FLAG_ENOSPC);
+      if (SIGNED) {  // give back the claims of the round that does not run
+        for (uint32_t i = tid; i < staged; i += kLT) a.cells[myOwn[i]].reserved0 = 0;
+        for (uint64_t j = gtid; j < ovf; j += gsize) a.cells[a.ocells[j]].reserved0 = 0;
+      }
       break;
     }
     // outputs of round t, grouped after the previous rounds
-    for (uint32_t i = tid; i < staged; i += kLT) a.out[listed + prefix + i] = myKeys[i];
-    for (uint64_t j = gtid; j < ovf; j += gsize) a.out[listed + total + j] = a.okeys[j];
+    for (uint32_t i = tid; i < staged; i += kLT) {
+      a.out[listed + prefix + i] = myKeys[i];
+      if (SIGNED) a.signs[listed + prefix + i] = static_cast<int8_t>(a.cells[myOwn[i]].count);
+    }
+    for (uint64_t j = gtid; j < ovf; j += gsize) {
+      a.out[listed + total + j] = a.okeys[j];
+      if (SIGNED) a.signs[listed + total + j] = static_cast<int8_t>(a.cells[a.ocells[j]].count);
+    }
     if (slot == 0 && tid == 0) {
       a.stats[t - 1] = K;
       ctrl->ovf_cand[(t + 1) & 1] = 0;  // consumed by the detect phase of round t
@@ -305,8 +327,12 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
       else
         a.ocand[(uint64_t)par * N + atomicAdd(&ctrl->ovf_cand[par], 1u)] = c;
     };
-    for (uint32_t i = tid; i < staged; i += kLT) delete_key<R>(a.h, a.cells, myKeys[i], myOwn[i], push);
-    for (uint64_t j = gtid; j < ovf; j += gsize) delete_key<R>(a.h, a.cells, a.okeys[j], a.ocells[j], push);
+    for (uint32_t i = tid; i < staged; i += kLT)
+      delete_key<R, SIGNED>(a.h, a.cells, myKeys[i], myOwn[i], push,
+                            SIGNED ? a.cells[myOwn[i]].count : 1);
+    for (uint64_t j = gtid; j < ovf; j += gsize)
+      delete_key<R, SIGNED>(a.h, a.cells, a.okeys[j], a.ocells[j], push,
+                            SIGNED ? a.cells[a.ocells[j]].count : 1);
     __syncthreads();
     const uint32_t ncand = s_cand < cb ? s_cand : cb;
     uint64_t dummy;
@@ -327,7 +353,8 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
         int32_t cnt;
         uint64_t ks, hs;
         load_cell(a.cells + c, &cnt, &ks, &hs);
-        if (owns<R>(a.h, a.cells, c, cnt, ks, hs, &bad)) stage(ks, c, npar);
+        if (owns<R, SIGNED>(a.h, a.cells, c, cnt, ks, hs, &bad) && (!SIGNED || claim_cell(a.cells, c)))
+          stage(ks, c, npar);
       }
       const uint32_t ovc =
           __hip_atomic_load(&ctrl->ovf_cand[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -336,7 +363,8 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
         int32_t cnt;
         uint64_t ks, hs;
         load_cell(a.cells + c, &cnt, &ks, &hs);
-        if (owns<R>(a.h, a.cells, c, cnt, ks, hs, &bad)) stage(ks, c, npar);
+        if (owns<R, SIGNED>(a.h, a.cells, c, cnt, ks, hs, &bad) && (!SIGNED || claim_cell(a.cells, c)))
+          stage(ks, c, npar);
       }
       if (bad) s_bad = 1;
     }
@@ -566,7 +594,24 @@ __global__ void __launch_bounds__(kLT) k_list_sub(ListArgs a) {
 }
 
 // summary = [listed, rounds, keys left, flags, workgroups in the persistent team, 0, 0, 0].
-__global__ void k_list_finish(const ListCtrl *ctrl, uint32_t r, uint64_t *summary) {
+// Signed listing: the cells left non-zero (summary[2]).
+__global__ void __launch_bounds__(kBlock) k_count_nonempty(const iblt_cell *cells, uint64_t n,
+                                                         ListCtrl *ctrl) {
+  __shared__ uint32_t lds[kBlock / kWave + 1];
+  uint32_t c = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kBlock) {
+    int32_t cnt;
+    uint64_t ks, hs;
+    load_cell(cells + i, &cnt, &ks, &hs);
+    c += (cnt != 0 || ks != 0 || hs != 0) ? 1u : 0u;
+  }
+  const uint32_t tot = block_sum(c, lds);
+  if (threadIdx.x == 0 && tot) atomicAdd(&ctrl->nonempty, (unsigned long long)tot);
+}
+
+__global__ void k_list_finish(const ListCtrl *ctrl, uint32_t r, uint64_t *summary,
+                              uint32_t signed_list) {
   if (threadIdx.x != 0) return;
   const long long total = (long long)ctrl->count_sum;
   const long long keys = total / (long long)r;
@@ -574,7 +619,7 @@ __global__ void k_list_finish(const ListCtrl *ctrl, uint32_t r, uint64_t *summar
   if (ctrl->bar.abort) flags |= PEEL_FLAG_TIMEOUT;
   summary[0] = ctrl->listed;
   summary[1] = ctrl->rounds;
-  summary[2] = (uint64_t)(keys - (long long)ctrl->listed);
+  summary[2] = signed_list ? (uint64_t)ctrl->nonempty : (uint64_t)(keys - (long long)ctrl->listed);
   summary[3] = flags;
   summary[4] = ctrl->team_size;
   summary[5] = summary[6] = summary[7] = 0;
@@ -912,9 +957,9 @@ bool desc_ok(const iblt_desc *d) {
 
 template <int R>
 peel_status launch_insert(const Hash &h, iblt_cell *cells, const uint64_t *keys, uint64_t nkeys,
-                          hipStream_t s) {
+                          hipStream_t s, int32_t sign) {
   const unsigned grid = grid_for(nkeys, kBlock, 1u << 16);
-  hipLaunchKernelGGL(k_insert<R>, dim3(grid), dim3(kBlock), 0, s, h, cells, keys, nkeys);
+  hipLaunchKernelGGL(k_insert<R>, dim3(grid), dim3(kBlock), 0, s, h, cells, keys, nkeys, sign);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }
@@ -924,8 +969,10 @@ peel_status launch_list(ListArgs &a, hipStream_t s, bool subtables) {
   if (device_info().debug) std::fprintf(stderr, "[peel] list grid %u\n", a.grid);
   if (subtables)
     hipLaunchKernelGGL(k_list_sub<R>, dim3(a.grid), dim3(kLT), 0, s, a);
+  else if (a.signed_list)
+    hipLaunchKernelGGL((k_list_persistent<R, true>), dim3(a.grid), dim3(kLT), 0, s, a);
   else
-    hipLaunchKernelGGL(k_list_persistent<R>, dim3(a.grid), dim3(kLT), 0, s, a);
+    hipLaunchKernelGGL((k_list_persistent<R, false>), dim3(a.grid), dim3(kLT), 0, s, a);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }
@@ -945,22 +992,38 @@ uint32_t batched_grid(uint32_t ntables) {
 
 using namespace peel;
 
-extern "C" peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
-                                   uint64_t nkeys, void *stream) {
+namespace peel {
+namespace {
+
+peel_status update_run(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
+                       uint64_t nkeys, void *stream, int32_t sign) {
   if (!desc_ok(desc) || !cells || (nkeys && !keys)) return PEEL_EINVAL;
   if (reinterpret_cast<uintptr_t>(cells) % 32) return PEEL_EINVAL;
   if (nkeys == 0) return PEEL_OK;
   const Hash h = make_hash(*desc);
   hipStream_t s = static_cast<hipStream_t>(stream);
   switch (desc->r) {
-    case 2: return launch_insert<2>(h, cells, keys, nkeys, s);
-    case 3: return launch_insert<3>(h, cells, keys, nkeys, s);
-    case 4: return launch_insert<4>(h, cells, keys, nkeys, s);
-    case 5: return launch_insert<5>(h, cells, keys, nkeys, s);
-    case 6: return launch_insert<6>(h, cells, keys, nkeys, s);
-    case 7: return launch_insert<7>(h, cells, keys, nkeys, s);
-    default: return launch_insert<8>(h, cells, keys, nkeys, s);
+    case 2: return launch_insert<2>(h, cells, keys, nkeys, s, sign);
+    case 3: return launch_insert<3>(h, cells, keys, nkeys, s, sign);
+    case 4: return launch_insert<4>(h, cells, keys, nkeys, s, sign);
+    case 5: return launch_insert<5>(h, cells, keys, nkeys, s, sign);
+    case 6: return launch_insert<6>(h, cells, keys, nkeys, s, sign);
+    case 7: return launch_insert<7>(h, cells, keys, nkeys, s, sign);
+    default: return launch_insert<8>(h, cells, keys, nkeys, s, sign);
   }
+}
+
+}  // namespace
+}  // namespace peel
+
+extern "C" peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
+                                   uint64_t nkeys, void *stream) {
+  return update_run(desc, cells, keys, nkeys, stream, 1);
+}
+
+extern "C" peel_status iblt_delete(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
+                                   uint64_t nkeys, void *stream) {
+  return update_run(desc, cells, keys, nkeys, stream, -1);
 }
 
 extern "C" size_t iblt_list_workspace(const iblt_desc *desc) {
@@ -972,9 +1035,10 @@ namespace {
 
 peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
                      uint64_t out_cap, uint64_t *round_stats, uint32_t max_rounds,
-                     uint64_t *summary, void *ws, size_t ws_bytes, void *stream, bool subtables) {
+                     uint64_t *summary, void *ws, size_t ws_bytes, void *stream, bool subtables,
+                     int8_t *out_signs = nullptr, bool signed_list = false) {
   if (!desc_ok(desc) || !cells || (out_cap && !out_keys) || !round_stats || !summary || !ws ||
-      max_rounds == 0)
+      max_rounds == 0 || (signed_list && out_cap && !out_signs))
     return PEEL_EINVAL;
   if (reinterpret_cast<uintptr_t>(cells) % 32) return PEEL_EINVAL;
   const ListLayout L = list_layout(desc->ncells, desc->workgroups);
@@ -1000,6 +1064,8 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
   a.out = out_keys;
   a.out_cap = out_cap;
   a.stats = round_stats;
+  a.signs = out_signs;
+  a.signed_list = signed_list ? 1u : 0u;
   a.limit = device_info().barrier_limit_ticks;
   a.quiet = device_info().team_quiet_ticks;
   a.ncells = static_cast<uint32_t>(desc->ncells);
@@ -1019,7 +1085,11 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
     default: st = launch_list<8>(a, s, subtables); break;
   }
   if (st) return st;
-  hipLaunchKernelGGL(k_list_finish, dim3(1), dim3(64), 0, s, a.ctrl, desc->r, summary);
+  if (signed_list)
+    hipLaunchKernelGGL(k_count_nonempty, dim3(grid_for(desc->ncells, kBlock * 8, 4096)),
+                       dim3(kBlock), 0, s, cells, desc->ncells, a.ctrl);
+  hipLaunchKernelGGL(k_list_finish, dim3(1), dim3(64), 0, s, a.ctrl, desc->r, summary,
+                     signed_list ? 1u : 0u);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }
@@ -1032,6 +1102,15 @@ extern "C" peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64
                                  uint64_t *summary, void *ws, size_t ws_bytes, void *stream) {
   return list_run(desc, cells, out_keys, out_cap, round_stats, max_rounds, summary, ws, ws_bytes,
                   stream, false);
+}
+
+extern "C" peel_status iblt_list_signed(const iblt_desc *desc, iblt_cell *cells,
+                                        uint64_t *out_keys, int8_t *out_signs, uint64_t out_cap,
+                                        uint64_t *round_stats, uint32_t max_rounds,
+                                        uint64_t *summary, void *ws, size_t ws_bytes,
+                                        void *stream) {
+  return list_run(desc, cells, out_keys, out_cap, round_stats, max_rounds, summary, ws, ws_bytes,
+                  stream, false, out_signs, true);
 }
 
 extern "C" peel_status iblt_list_subtables(const iblt_desc *desc, iblt_cell *cells,

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_version_and_strerror(L):
-    assert L.peel_abi_version() == 5
+    assert L.peel_abi_version() == 6
     for code in range(-6, 1):
         assert L.peel_strerror(code)
     assert L.peel_strerror(-99) == b"unknown status"
