@@ -62,6 +62,7 @@ constexpr uint32_t kOwnMaxE = 65536;  // owned edges (LDS alive and claimed bits
 constexpr uint32_t kOwnMaxT = 1024;   // owner workgroups (LDS per-destination counters)
 constexpr uint64_t kDenseRatio = 3;   // dense round when |F_{t-1}| * 3 >= alive edges
 constexpr uint32_t kNoVertex = 0xffffffffu;
+constexpr int kLU = 4;                // queue entries per thread whose loads are in flight
 
 enum : uint32_t { kModeUndecided = 0, kModeOwnerDone = 1, kModeGlobal = 2 };
 enum : uint32_t { kRoundsAuto = 0, kRoundsDense = 1, kRoundsSparse = 2 };
@@ -346,16 +347,30 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         s_start[tid] = st;
         s_pre[tid] = ex;
         __syncthreads();
-        for (uint32_t j = tid; j < tot; j += kOT) {
-          // the last list whose start is <= j holds incidence j
-          uint32_t lo = 0, hi = kOT;
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s_pre[mid] <= j) lo = mid; else hi = mid;
+        for (uint32_t j0 = tid; j0 < tot; j0 += kLU * kOT) {
+          uint32_t e[kLU];
+#pragma unroll
+          for (int u = 0; u < kLU; ++u) {
+            const uint32_t j = j0 + u * kOT;
+            e[u] = kNoVertex;
+            if (j < tot) {
+              // the last list whose start is <= j holds incidence j
+              uint32_t lo = 0, hi = kOT;
+              while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_pre[mid] <= j) lo = mid; else hi = mid;
+              }
+              e[u] = a.inc[s_start[lo] + (j - s_pre[lo])];
+            }
           }
-          const uint32_t e = a.inc[s_start[lo] + (j - s_pre[lo])];
-          claims[nc + j] = e;
-          atomicAdd(&cnt[e / Eb], 1u);
+#pragma unroll
+          for (int u = 0; u < kLU; ++u) {
+            const uint32_t j = j0 + u * kOT;
+            if (j < tot) {
+              claims[nc + j] = e[u];
+              atomicAdd(&cnt[e[u] / Eb], 1u);
+            }
+          }
         }
         nc += tot;
         __syncthreads();
@@ -365,9 +380,16 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         cur[d] = c ? d * Eb * R + atomicAdd(&ctrl->qh_claim[d], c) : 0u;
       }
       __syncthreads();
-      for (uint32_t i = tid; i < nc; i += kOT) {
-        const uint32_t e = claims[i];
-        a.qclaim[atomicAdd(&cur[e / Eb], 1u)] = e;
+      for (uint32_t i0 = tid; i0 < nc; i0 += kLU * kOT) {
+        uint32_t e[kLU];
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+          const uint32_t i = i0 + u * kOT;
+          e[u] = i < nc ? claims[i] : kNoVertex;
+        }
+#pragma unroll
+        for (int u = 0; u < kLU; ++u)
+          if (e[u] != kNoVertex) a.qclaim[atomicAdd(&cur[e[u] / Eb], 1u)] = e[u];
       }
     }
     // The barrier sums |F_t| and, in subtables mode, the waiting bits (high word).
@@ -475,9 +497,19 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         __syncthreads();
         won = s_w;
       }
-      for (uint32_t i = tid; nclaims > (uint32_t)kOT && i < nclaims; i += kOT) {
-        const uint32_t le = myClaims[i] - (uint32_t)e0;
-        atomicOr(&claimed[le >> 5], 1u << (le & 31));
+      for (uint32_t i0 = tid; nclaims > (uint32_t)kOT && i0 < nclaims; i0 += kLU * kOT) {
+        uint32_t e[kLU];
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+          const uint32_t i = i0 + u * kOT;
+          e[u] = i < nclaims ? myClaims[i] : kNoVertex;
+        }
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+          if (e[u] == kNoVertex) continue;
+          const uint32_t le = e[u] - (uint32_t)e0;
+          atomicOr(&claimed[le >> 5], 1u << (le & 31));
+        }
       }
       __syncthreads();
       const uint32_t nw = nclaims > (uint32_t)kOT ? (uint32_t)((e1 - e0 + 31) / 32) : 0u;
@@ -494,22 +526,35 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         s_start[tid] = dying;
         s_pre[tid] = ex;
         __syncthreads();
-        for (uint32_t j = tid; j < tot; j += kOT) {
-          uint32_t lo = 0, hi = kOT;
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s_pre[mid] <= j) lo = mid; else hi = mid;
+        constexpr int kEU = R <= 4 ? 2 : 1;  // dying edges per thread whose rows are in flight
+        for (uint32_t j0 = tid; j0 < tot; j0 += kEU * kOT) {
+          uint64_t e[kEU];
+          uint32_t ids[kEU][R];
+#pragma unroll
+          for (int u = 0; u < kEU; ++u) {
+            const uint32_t j = j0 + u * kOT;
+            if (j < tot) {
+              uint32_t lo = 0, hi = kOT;
+              while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_pre[mid] <= j) lo = mid; else hi = mid;
+              }
+              e[u] = e0 + 32ull * (w0 + lo) + nth_set_bit(s_start[lo], j - s_pre[lo]);
+              const uint32_t *row = a.edges + e[u] * R;
+#pragma unroll
+              for (int q = 0; q < R; ++q) ids[u][q] = row[q];
+            }
           }
-          const uint64_t e = e0 + 32ull * (w0 + lo) + nth_set_bit(s_start[lo], j - s_pre[lo]);
-          a.er[e] = t;
-          const uint32_t *row = a.edges + e * R;
-          uint32_t ids[R];
 #pragma unroll
-          for (int q = 0; q < R; ++q) ids[q] = row[q];
+          for (int u = 0; u < kEU; ++u) {
+            const uint32_t j = j0 + u * kOT;
+            if (j >= tot) continue;
+            a.er[e[u]] = t;
 #pragma unroll
-          for (int q = 0; q < R; ++q) {
-            myStage[(uint64_t)(won + j) * R + q] = ids[q];
-            if (ids[q] < n) atomicAdd(&cnt[ids[q] / Vb], 1u);
+            for (int q = 0; q < R; ++q) {
+              myStage[(uint64_t)(won + j) * R + q] = ids[u][q];
+              if (ids[u][q] < n) atomicAdd(&cnt[ids[u][q] / Vb], 1u);
+            }
           }
         }
         won += tot;
@@ -525,9 +570,16 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       cur[d] = c ? a.offsets[dv] + atomicAdd(&ctrl->qh_dec[d], c) : 0u;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < won * R; i += kOT) {
-      const uint32_t u = myStage[i];
-      if (u < n) a.qdec[atomicAdd(&cur[u / Vb], 1u)] = u;
+    for (uint32_t i0 = tid; i0 < won * R; i0 += kLU * kOT) {
+      uint32_t x[kLU];
+#pragma unroll
+      for (int u = 0; u < kLU; ++u) {
+        const uint32_t i = i0 + u * kOT;
+        x[u] = i < won * R ? myStage[i] : kNoVertex;
+      }
+#pragma unroll
+      for (int u = 0; u < kLU; ++u)
+        if (x[u] < n) a.qdec[atomicAdd(&cur[x[u] / Vb], 1u)] = x[u];
     }
     uint64_t et;
     if (!sum_barrier(&ctrl->bar, T, slot, won, &epoch, a.limit, &et, ctrl->stamp)) return;
@@ -543,21 +595,31 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     }
     __syncthreads();
     const uint32_t ndec = s_w;
-    for (uint32_t i = tid; i < ndec; i += kOT) {
-      const uint32_t u = myDecs[i];
-      const uint32_t lv = u - v0;
-      // a vertex removed this round (its edges die with it) keeps its round
-      if ((gone[lv >> 5] >> (lv & 31)) & 1u) continue;
-      const uint32_t sh = 8 * (lv & 3);
-      uint32_t old;
-      if (((deg8[lv >> 2] >> sh) & 255u) == 255u)
-        old = atomicSub(&a.deg[u], 1u);
-      else
-        old = (atomicSub(&deg8[lv >> 2], 1u << sh) >> sh) & 255u;
-      if (old == k) {
-        atomicOr(&fbl[lv >> 5], 1u << (lv & 31));
-        const uint32_t p = atomicAdd(&s_n, 1u);
-        if (p < (uint32_t)kOT) s_start[p] = u;
+    for (uint32_t i0 = tid; i0 < ndec; i0 += kLU * kOT) {
+      uint32_t us[kLU];
+#pragma unroll
+      for (int q = 0; q < kLU; ++q) {
+        const uint32_t i = i0 + q * kOT;
+        us[q] = i < ndec ? myDecs[i] : kNoVertex;
+      }
+#pragma unroll
+      for (int q = 0; q < kLU; ++q) {
+        const uint32_t u = us[q];
+        if (u == kNoVertex) continue;
+        const uint32_t lv = u - v0;
+        // a vertex removed this round (its edges die with it) keeps its round
+        if ((gone[lv >> 5] >> (lv & 31)) & 1u) continue;
+        const uint32_t sh = 8 * (lv & 3);
+        uint32_t old;
+        if (((deg8[lv >> 2] >> sh) & 255u) == 255u)
+          old = atomicSub(&a.deg[u], 1u);
+        else
+          old = (atomicSub(&deg8[lv >> 2], 1u << sh) >> sh) & 255u;
+        if (old == k) {
+          atomicOr(&fbl[lv >> 5], 1u << (lv & 31));
+          const uint32_t p = atomicAdd(&s_n, 1u);
+          if (p < (uint32_t)kOT) s_start[p] = u;
+        }
       }
     }
     __syncthreads();
