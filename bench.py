@@ -399,6 +399,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-iblt", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="also time every c of the n=2^24 sweep")
+    ap.add_argument("--no-subtables", action="store_true",
+                    help="skip the subtables peel (profiles of the main workload alone)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=5000, help="measured requests per rate")
@@ -436,12 +438,13 @@ def main():
         "rounds": kc["rounds"], "edge_rounds": kc["edge_rounds"],
         "core_vertices": kc["core_vertices"],
     }
-    # the paper's own schedule (peeling with subtables) on the same workload
-    sb = bench_kcore(spec, max(3, args.steps // 2), 1, subtables=True)
-    extra["subtables"] = {
-        "peel_ms": sb["peel_ms"], "subrounds": sb["rounds"], "edge_subrounds": sb["edge_rounds"],
-        "peel_edges_per_s": sb["m_removed"] / (sb["peel_ms"] * 1e-3),
-        "vs_rounds_peel_ms": kc["peel_ms"]}
+    if not args.no_subtables:
+        # the paper's own schedule (peeling with subtables) on the same workload
+        sb = bench_kcore(spec, max(3, args.steps // 2), 1, subtables=True)
+        extra["subtables"] = {
+            "peel_ms": sb["peel_ms"], "subrounds": sb["rounds"], "edge_subrounds": sb["edge_rounds"],
+            "peel_edges_per_s": sb["m_removed"] / (sb["peel_ms"] * 1e-3),
+            "vs_rounds_peel_ms": kc["peel_ms"]}
     if not args.no_batched:
         log("batched IBLT listing (4096 tables)")
         extra["batched"] = bench_batched(configs.batched_main(), 3)
