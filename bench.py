@@ -448,6 +448,8 @@ def main():
     if not args.no_batched:
         log("batched IBLT listing (4096 tables)")
         extra["batched"] = bench_batched(configs.batched_main(), 3)
+        log("batched IBLT listing, 5% of the tables above threshold")
+        extra["batched_partial"] = bench_batched(configs.batched_partial(), 3)
     if not args.no_iblt:
         log("IBLT 2^24 cells")
         extra["iblt"] = [bench_iblt(configs.iblt_main(), 5),

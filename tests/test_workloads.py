@@ -59,3 +59,17 @@ def test_config_sizes():
     b = configs.batched_main().draw()
     assert len(b) == 4096
     assert all(2 ** 10 - 1 <= N <= 2 ** 20 + 1 for N, _, _, _ in b)
+
+
+def test_partial_batch():
+    # a seeded ~5% of the tables move above threshold (load 1.0-1.2 c*); the
+    # rest are the plain batch's tables, unchanged
+    main = configs.batched_main().draw()
+    part = configs.batched_partial().draw()
+    cs = configs.cstar(2, 3)
+    hot = [i for i in range(len(main)) if main[i] != part[i]]
+    assert 0.04 * len(main) <= len(hot) <= 0.06 * len(main)
+    for i in hot:
+        N, m, ks, ts = part[i]
+        assert (N, ks, ts) == main[i][0:1] + main[i][2:]
+        assert 1.0 * cs * N - 1 <= m <= 1.2 * cs * N + 1

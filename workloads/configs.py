@@ -114,6 +114,9 @@ class BatchSpec:
     load_hi: float
     seed: int = 1
     tables: tuple = field(default=(), compare=False)
+    hot_frac: float = 0.0  # a seeded share of tables drawn above threshold instead
+    hot_lo: float = 1.0
+    hot_hi: float = 1.2
 
     def draw(self, seed: int | None = None):
         """[(ncells, nkeys, key_seed, table_seed)] for every table."""
@@ -123,11 +126,18 @@ class BatchSpec:
         u = gen.splitmix64(st, idx).reshape(self.ntables, 3)
         unit = (u >> np.uint64(11)).astype(np.float64) / float(1 << 53)
         cs = cstar(2, self.r)
+        if self.hot_frac > 0:
+            # a stream of its own, so the other tables are those of the plain batch
+            hs = gen.stream_seed(s, 0x9E3779B97F4A7C15)
+            hu = gen.splitmix64(hs, np.arange(2 * self.ntables, dtype=np.uint64))
+            hot = ((hu >> np.uint64(11)).astype(np.float64) / float(1 << 53)).reshape(self.ntables, 2)
         out = []
         for i in range(self.ntables):
             N = int(round(2.0 ** (self.log2_lo + (self.log2_hi - self.log2_lo) * unit[i, 0])))
             N = max(N, self.r)
             load = (self.load_lo + (self.load_hi - self.load_lo) * unit[i, 1]) * cs
+            if self.hot_frac > 0 and hot[i, 0] < self.hot_frac:
+                load = (self.hot_lo + (self.hot_hi - self.hot_lo) * hot[i, 1]) * cs
             m = int(round(load * N))
             kseed = int(u[i, 2])
             out.append((N, m, kseed, gen.table_seed(kseed)))
@@ -136,6 +146,13 @@ class BatchSpec:
 
 def batched_main() -> BatchSpec:
     return BatchSpec("iblt_batched_4096_r3", 4096, 3, 10.0, 20.0, 0.5, 0.8)
+
+
+def batched_partial() -> BatchSpec:
+    """The 4096-table batch with a seeded 5% of its tables at load 1.0-1.2 c*:
+    those keep a 2-core, so the batch exercises partial listing."""
+    return BatchSpec("iblt_batched_4096_r3_partial5", 4096, 3, 10.0, 20.0, 0.5, 0.8,
+                     hot_frac=0.05, hot_lo=1.0, hot_hi=1.2)
 
 
 @dataclass(frozen=True)
