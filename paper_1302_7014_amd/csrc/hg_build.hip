@@ -14,8 +14,8 @@
 //                   the (bucket, tile) counts, both bucket-major: the second
 //                   gives every (bucket, tile) run its final place;
 //   3. bin scatter  each tile writes its (vertex, edge) pairs into its slice of
-//                   every super-bucket (LDS cursors; a few hundred open lines
-//                   per workgroup);
+//                   every super-bucket: 8192 pairs at a time are sorted by
+//                   super-bucket in LDS and stored as contiguous runs;
 //   4. split        one workgroup per (super-bucket, group of tiles) moves its
 //                   pairs to their (bucket, tile) runs (LDS cursors);
 //   5. bucket build one workgroup per bucket counts degrees in LDS, scans them
@@ -44,6 +44,10 @@ constexpr int kSplitTiles = 32;                 // tiles per split workgroup
 constexpr uint32_t kStageCap = 28672;           // incidences of a bucket staged in LDS
 constexpr uint64_t kTileEdges = 16384;          // edges per bin tile
 constexpr int kBT = 1024;                       // threads per workgroup in the bin kernels
+constexpr int kRowsU = 4;                       // edge rows per thread in flight in the count
+constexpr uint32_t kSortPairs = 8192;           // pairs sorted in LDS per scatter chunk
+constexpr int kPairsU = 4;                      // pairs per thread in flight in the bucket build
+constexpr uint32_t kNone = ~0u;
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 __device__ inline uint64_t ceil_div_dev(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -172,15 +176,25 @@ __global__ void __launch_bounds__(kBT)
   const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
   bool bad = false;
-  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBT) {
-    const uint32_t *row = edges + e * R;
+  for (uint64_t eb = e0 + threadIdx.x; eb < e1; eb += kRowsU * kBT) {
+    uint32_t ids[kRowsU][R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const uint32_t v = row[j];
-      if (v < n)
-        atomicAdd(&h[v >> kBinShift], 1u);
-      else
-        bad = true;
+    for (int u = 0; u < kRowsU; ++u) {
+      const uint64_t e = eb + (uint64_t)u * kBT;
+#pragma unroll
+      for (int j = 0; j < R; ++j) ids[u][j] = e < e1 ? edges[e * R + j] : kNone;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsU; ++u) {
+      if (eb + (uint64_t)u * kBT >= e1) continue;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint32_t v = ids[u][j];
+        if (v < n)
+          atomicAdd(&h[v >> kBinShift], 1u);
+        else
+          bad = true;
+      }
     }
   }
   if (bad) atomicOr(&info[0], PEEL_FLAG_ERANGE);
@@ -194,37 +208,63 @@ __global__ void __launch_bounds__(kBT)
   }
 }
 
-// pairs[...] = (edge << 32 | vertex) grouped by super-bucket, each tile in its own slice.
+// pairs[...] = (edge << 32 | vertex) grouped by super-bucket, each tile in its own
+// slice of every super-bucket.  A tile is taken kSortPairs incidences at a time:
+// they are ranked per super-bucket and sorted in LDS, then written out as one
+// run per super-bucket, so neighbouring lanes store to neighbouring addresses.
 template <int R>
 __global__ void __launch_bounds__(kBT)
-    k_bin_scatter(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nb,
+    k_bin_scatter(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nsb,
                   uint64_t ntiles, const uint32_t *__restrict__ hist, uint64_t *pairs) {
-  __shared__ uint32_t cur[kMaxSuper];
-  for (uint32_t b = threadIdx.x; b < nb; b += kBT) cur[b] = hist[(uint64_t)b * ntiles + blockIdx.x];
-  __syncthreads();
+  constexpr uint32_t kCE = kSortPairs / R;            // edges per chunk
+  constexpr int kEPT = (int)((kCE + kBT - 1) / kBT);  // edges per thread per chunk
+  __shared__ uint64_t sp[kSortPairs];
+  __shared__ uint32_t cur[kMaxSuper];  // next place of this tile in each super-bucket
+  __shared__ uint32_t cnt[kMaxSuper];  // this chunk's pairs per super-bucket
+  __shared__ uint32_t st[kMaxSuper];   // their exclusive scan
+  __shared__ uint32_t lds[kBT / kWave + 1];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t b = tid; b < nsb; b += kBT) cur[b] = hist[(uint64_t)b * ntiles + blockIdx.x];
   const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
-  constexpr int kU = 4;  // rows per thread in flight
-  for (uint64_t eb = e0 + threadIdx.x; eb < e1; eb += kU * kBT) {
-    uint32_t ids[kU][R];
+  for (uint64_t c0 = e0; c0 < e1; c0 += kCE) {
+    const uint64_t c1 = c0 + kCE < e1 ? c0 + kCE : e1;
+    for (uint32_t b = tid; b < nsb; b += kBT) cnt[b] = 0;
+    __syncthreads();
+    uint32_t ids[kEPT][R], rk[kEPT][R];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const uint64_t e = eb + (uint64_t)u * kBT;
+    for (int u = 0; u < kEPT; ++u) {
+      const uint64_t e = c0 + (uint64_t)u * kBT + tid;
 #pragma unroll
-      for (int j = 0; j < R; ++j) ids[u][j] = e < e1 ? edges[e * R + j] : ~0u;
+      for (int j = 0; j < R; ++j) ids[u][j] = e < c1 ? edges[e * R + j] : kNone;
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const uint64_t e = eb + (uint64_t)u * kBT;
+    for (int u = 0; u < kEPT; ++u)
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if (ids[u][j] < n) rk[u][j] = atomicAdd(&cnt[ids[u][j] >> kSupShift], 1u);
+    __syncthreads();
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<kBT>(tid < nsb ? cnt[tid] : 0u, &tot, lds);
+    if (tid < nsb) st[tid] = ex;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+      const uint64_t e = c0 + (uint64_t)u * kBT + tid;
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const uint32_t v = ids[u][j];
-        if (v < n) {
-          const uint32_t pos = atomicAdd(&cur[v >> kSupShift], 1u);
-          pairs[pos] = (e << 32) | v;
-        }
+        if (v < n) sp[st[v >> kSupShift] + rk[u][j]] = (e << 32) | v;
       }
     }
+    __syncthreads();
+    for (uint32_t i = tid; i < tot; i += kBT) {
+      const uint64_t pr = sp[i];
+      const uint32_t b = static_cast<uint32_t>(pr) >> kSupShift;
+      pairs[cur[b] + (i - st[b])] = pr;
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < nsb; b += kBT) cur[b] += cnt[b];
   }
 }
 
@@ -282,8 +322,17 @@ __global__ void __launch_bounds__(kBT)
   const uint32_t nv = (n - v0) < (uint32_t)kBinV ? (n - v0) : (uint32_t)kBinV;
   for (uint32_t i = threadIdx.x; i < (uint32_t)(kBinV + kBinV / 32); i += kBT) cnt[i] = 0;
   __syncthreads();
-  for (uint32_t p = base + threadIdx.x; p < end; p += kBT)
-    atomicAdd(&cnt[pad(static_cast<uint32_t>(pairs[p]) - v0)], 1u);
+  for (uint32_t p0 = base + threadIdx.x; p0 < end; p0 += kPairsU * kBT) {
+    uint32_t vs[kPairsU];
+#pragma unroll
+    for (int u = 0; u < kPairsU; ++u) {
+      const uint32_t p = p0 + u * kBT;
+      vs[u] = p < end ? static_cast<uint32_t>(pairs[p]) : kNone;
+    }
+#pragma unroll
+    for (int u = 0; u < kPairsU; ++u)
+      if (vs[u] != kNone) atomicAdd(&cnt[pad(vs[u] - v0)], 1u);
+  }
   __syncthreads();
   // exclusive scan of cnt[0..kBinV): kPer consecutive counts per thread
   constexpr int kPer = kBinV / kBT;
@@ -314,10 +363,19 @@ __global__ void __launch_bounds__(kBT)
   __syncthreads();
   const uint32_t total_b = end - base;
   if (total_b <= kStageCap) {
-    for (uint32_t p = base + threadIdx.x; p < end; p += kBT) {
-      const uint64_t pr = pairs[p];
-      const uint32_t pos = atomicAdd(&cnt[pad(static_cast<uint32_t>(pr) - v0)], 1u);
-      stage[pos] = static_cast<uint32_t>(pr >> 32);
+    for (uint32_t p0 = base + threadIdx.x; p0 < end; p0 += kPairsU * kBT) {
+      uint64_t pr[kPairsU];
+#pragma unroll
+      for (int u = 0; u < kPairsU; ++u) {
+        const uint32_t p = p0 + u * kBT;
+        pr[u] = p < end ? pairs[p] : ~0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kPairsU; ++u) {
+        if (p0 + u * kBT >= end) continue;
+        const uint32_t pos = atomicAdd(&cnt[pad(static_cast<uint32_t>(pr[u]) - v0)], 1u);
+        stage[pos] = static_cast<uint32_t>(pr[u] >> 32);
+      }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < total_b; i += kBT) inc[base + i] = stage[i];
