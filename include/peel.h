@@ -53,7 +53,8 @@ typedef int32_t peel_status;
 #define PEEL_FLAG_EROUNDS 0x2u
 #define PEEL_FLAG_ENOSPC 0x4u
 #define PEEL_FLAG_ECORRUPT 0x8u
-#define PEEL_FLAG_TIMEOUT 0x10u /* a device-wide barrier waited past its limit */
+#define PEEL_FLAG_TIMEOUT 0x10u /* a device-wide barrier waited past its limit; */
+                                /* the call's other outputs are then undefined  */
 
 /* Human-readable name of a status code; never NULL. */
 const char *peel_strerror(peel_status s);

@@ -62,6 +62,7 @@ constexpr uint32_t kOwnMaxE = 65536;  // owned edges (LDS alive and claimed bits
 constexpr uint32_t kOwnMaxT = 1024;   // owner workgroups (LDS per-destination counters)
 constexpr uint64_t kDenseRatio = 3;   // dense round when |F_{t-1}| * 3 >= alive edges
 constexpr uint32_t kNoVertex = 0xffffffffu;
+constexpr uint32_t kNib = 15;         // escape value of the owner engine's 4-bit fields
 constexpr int kLU = 4;                // queue entries per thread whose loads are in flight
 
 enum : uint32_t { kModeUndecided = 0, kModeOwnerDone = 1, kModeGlobal = 2 };
@@ -143,13 +144,16 @@ __device__ inline uint32_t nth_set_bit(uint32_t x, uint32_t r) {
 
 template <int R>
 __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
-  // One byte per owned vertex: its degree while alive (255 = held in the global
-  // degree array instead), its removal round once removed (255 = t >= 255,
-  // written to vertex_round directly).  `gone` marks the removed vertices.
-  __shared__ uint32_t deg8[kOwnMaxV / 4];
+  // Four bits per owned vertex: its degree while alive (kNib = held in the
+  // global degree array instead), its removal round once removed (kNib = t >=
+  // kNib, written to vertex_round directly).  `gone` marks the removed vertices.
+  __shared__ uint32_t deg4[kOwnMaxV / 8];
   __shared__ uint32_t gone[kOwnMaxV / 32];
   __shared__ uint32_t alive[kOwnMaxE / 32];
   __shared__ uint32_t claimed[kOwnMaxE / 32];  // edges claimed this round
+  // Four bits per owned edge: its removal round (0 = alive; kNib = t >= kNib,
+  // written to edge_round directly).  edge_round is written in order at the end.
+  __shared__ uint32_t er4[kOwnMaxE / 8];
   __shared__ uint32_t cnt[kOwnMaxT];
   __shared__ uint32_t cur[kOwnMaxT];
   __shared__ uint32_t s_start[kOT];
@@ -194,25 +198,25 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     alive[w] = bits;
     claimed[w] = 0;
   }
+  for (uint32_t w = tid; w < (Eb + 7) / 8; w += kOT) er4[w] = 0;
   __syncthreads();
-  for (uint32_t w = tid; w < (Vb + 3) / 4; w += kOT) {
+  for (uint32_t w = tid; w < (Vb + 7) / 8; w += kOT) {
     uint32_t word = 0, low = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t v = v0 + 4 * w + i;
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t v = v0 + 8 * w + i;
       if (v < v1) {
         const uint32_t d = a.deg[v];
-        word |= (d >= 255u ? 255u : d) << (8 * i);
+        word |= (d >= kNib ? kNib : d) << (4 * i);
         if (d < k) low |= 1u << i;
       }
     }
-    deg8[w] = word;
+    deg4[w] = word;
     if (low) {
-      atomicOr(&fbl[w >> 3], low << (4 * (w & 7)));
+      atomicOr(&fbl[w >> 2], low << (8 * (w & 3)));
       atomicAdd(&s_p, static_cast<uint32_t>(__popc(low)));
     }
   }
-  for (uint64_t e = e0 + tid; e < e1; e += kOT) a.er[e] = 0;
   if (slot == 0)
     for (uint64_t i = tid; i < 2ull * a.max_rounds; i += kOT) a.stats[i] = 0;
   if (tid == 0) s_n = ~0u;  // F_1 is taken from the bitmap
@@ -225,16 +229,26 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   uint32_t pend = s_p;
 
   // v leaves in round t with every edge it still holds, so its final degree
-  // is 0; its byte now keeps the round (vertex_round is written at the end)
+  // is 0; its nibble now keeps the round (vertex_round is written at the end)
   auto mark_removed = [&](uint32_t v, uint32_t lv, uint32_t t) {
-    const uint32_t sh = 8 * (lv & 3);
+    const uint32_t sh = 4 * (lv & 7);
     atomicOr(&gone[lv >> 5], 1u << (lv & 31));
-    atomicAnd(&deg8[lv >> 2], ~(255u << sh));
-    if (t < 255u)
-      atomicOr(&deg8[lv >> 2], t << sh);
+    atomicAnd(&deg4[lv >> 3], ~(kNib << sh));
+    if (t < kNib)
+      atomicOr(&deg4[lv >> 3], t << sh);
     else {
-      atomicOr(&deg8[lv >> 2], 255u << sh);
+      atomicOr(&deg4[lv >> 3], kNib << sh);
       a.vr[v] = t;
+    }
+  };
+  // my edge le dies in round t (its nibble is 0 until now)
+  auto mark_edge = [&](uint32_t le, uint32_t t) {
+    const uint32_t sh = 4 * (le & 7);
+    if (t < kNib) {
+      atomicOr(&er4[le >> 3], t << sh);
+    } else {
+      atomicOr(&er4[le >> 3], kNib << sh);
+      a.er[e0 + le] = t;
     }
   };
 
@@ -335,9 +349,9 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         if (c0 + tid < fcnt) {
           const uint32_t v = myF[c0 + tid];
           const uint32_t lv = v - v0;
-          const uint32_t d8 = (deg8[lv >> 2] >> (8 * (lv & 3))) & 255u;
+          const uint32_t d4 = (deg4[lv >> 3] >> (4 * (lv & 7))) & kNib;
           mark_removed(v, lv, t);
-          if (d8 != 0) {  // a vertex of degree 0 holds no alive edge
+          if (d4 != 0) {  // a vertex of degree 0 holds no alive edge
             st = a.offsets[v];
             len = a.offsets[v + 1] - st;
           }
@@ -455,7 +469,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
           const uint32_t w = wave_append(die, &s_w);
           if (die) {
             atomicAnd(&alive[le >> 5], ~(1u << (le & 31)));
-            a.er[e0 + le] = t;
+            mark_edge(le, t);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
               myStage[(uint64_t)w * R + j] = ids[u][j];
@@ -483,7 +497,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         }
         const uint32_t w = wave_append(win, &s_w);
         if (win) {
-          a.er[e] = t;
+          mark_edge(e - (uint32_t)e0, t);
           const uint32_t *row = a.edges + (uint64_t)e * R;
           uint32_t ids[R];
 #pragma unroll
@@ -549,7 +563,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
           for (int u = 0; u < kEU; ++u) {
             const uint32_t j = j0 + u * kOT;
             if (j >= tot) continue;
-            a.er[e[u]] = t;
+            mark_edge((uint32_t)(e[u] - e0), t);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
               myStage[(uint64_t)(won + j) * R + q] = ids[u][q];
@@ -609,12 +623,12 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         const uint32_t lv = u - v0;
         // a vertex removed this round (its edges die with it) keeps its round
         if ((gone[lv >> 5] >> (lv & 31)) & 1u) continue;
-        const uint32_t sh = 8 * (lv & 3);
+        const uint32_t sh = 4 * (lv & 7);
         uint32_t old;
-        if (((deg8[lv >> 2] >> sh) & 255u) == 255u)
+        if (((deg4[lv >> 3] >> sh) & kNib) == kNib)
           old = atomicSub(&a.deg[u], 1u);
         else
-          old = (atomicSub(&deg8[lv >> 2], 1u << sh) >> sh) & 255u;
+          old = (atomicSub(&deg4[lv >> 3], 1u << sh) >> sh) & kNib;
         if (old == k) {
           atomicOr(&fbl[lv >> 5], 1u << (lv & 31));
           const uint32_t p = atomicAdd(&s_n, 1u);
@@ -629,14 +643,19 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   // ---- epilogue: removal rounds and final degrees, written in order ----------
   for (uint32_t v = v0 + tid; v < v1; v += kOT) {
     const uint32_t lv = v - v0;
-    const uint32_t b = (deg8[lv >> 2] >> (8 * (lv & 3))) & 255u;
+    const uint32_t b = (deg4[lv >> 3] >> (4 * (lv & 7))) & kNib;
     if ((gone[lv >> 5] >> (lv & 31)) & 1u) {
       a.deg[v] = 0;
-      if (b != 255u) a.vr[v] = b;
+      if (b != kNib) a.vr[v] = b;
     } else {
       a.vr[v] = 0;
-      if (b != 255u) a.deg[v] = b;
+      if (b != kNib) a.deg[v] = b;
     }
+  }
+  for (uint64_t e = e0 + tid; e < e1; e += kOT) {
+    const uint32_t le = (uint32_t)(e - e0);
+    const uint32_t x = (er4[le >> 3] >> (4 * (le & 7))) & kNib;
+    if (x != kNib) a.er[e] = x;
   }
   if (slot == 0 && tid == 0) {
     ctrl->rounds = last;

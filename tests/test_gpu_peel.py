@@ -85,6 +85,12 @@ def test_degenerate_inputs(rounds):
         (8, 2, np.array([[j] * 8 for j in range(8)], np.uint32)),  # r = 8, loops
         # one CSR bucket with more incidences than the build stages in LDS
         (100, 3, np.random.default_rng(3).integers(0, 100, size=(12000, 4)).astype(np.uint32)),
+        # degrees and k around and above 15, where the owner engine keeps a
+        # vertex's degree in the global array instead of four bits of LDS
+        (1000, 15, np.random.default_rng(4).integers(0, 1000, size=(3750, 4)).astype(np.uint32)),
+        (300, 16, np.random.default_rng(5).integers(0, 300, size=(1200, 4)).astype(np.uint32)),
+        (300, 20, np.random.default_rng(6).integers(0, 300, size=(2300, 4)).astype(np.uint32)),
+        (300, 20, np.random.default_rng(7).integers(0, 300, size=(2350, 4)).astype(np.uint32)),
     ]
     for n, k, e in cases:
         say("degenerate", rounds, n, k, e.shape)

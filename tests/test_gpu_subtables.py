@@ -40,7 +40,10 @@ def test_small_and_degenerate(engine):
              (3, 1, np.array([[0, 1, 2]], np.uint32)),
              (3, 2, np.array([[0, 1, 2], [0, 1, 2]], np.uint32)),
              (7, 2, np.array([[0, 1, 2], [0, 3, 4], [0, 5, 6]], np.uint32)),
-             (2, 2, np.array([[0, 0], [1, 1], [0, 1]], np.uint32))]
+             (2, 2, np.array([[0, 0], [1, 1], [0, 1]], np.uint32)),
+             (1000, 15, np.random.default_rng(4).integers(0, 1000, size=(3750, 4)).astype(np.uint32)),
+             (300, 20, np.random.default_rng(6).integers(0, 300, size=(2300, 4)).astype(np.uint32)),
+             (300, 20, np.random.default_rng(7).integers(0, 300, size=(2350, 4)).astype(np.uint32))]
     for _ in range(30):
         r = int(rng.integers(2, 9))
         k = int(rng.integers(1, 5))
