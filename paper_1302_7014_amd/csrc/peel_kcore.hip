@@ -12,11 +12,11 @@
 // Owner engine (the default).  Device-scope atomics run at a fixed ~27 G/s on
 // this GPU whatever the working set, so the owner engine keeps the per-edge
 // work in LDS.  Each of T workgroups (one per CU) owns a range of Vb vertices,
-// whose degrees it holds as bytes in LDS, and a range of Eb edges, whose
-// "alive" bits it holds in LDS.  A round is two message exchanges through
-// per-destination queues in HBM (a workgroup counts its messages per
-// destination in LDS, reserves space with one atomic per destination, then
-// writes them):
+// whose degrees (then removal rounds) it holds as four-bit fields in LDS, and
+// a range of Eb edges, whose "alive" bits and removal rounds it holds in LDS.
+// A round is two message exchanges through per-destination queues in HBM (a
+// workgroup counts its messages per destination in LDS, reserves space with
+// one atomic per destination, then writes them):
 //   claims      each owner sends, for every vertex of its frontier F_t, one
 //               claim per incident edge to that edge's owner;
 //   decrements  each edge owner clears the alive bit of every claimed edge
@@ -26,8 +26,10 @@
 //               decrement that takes a degree from k to k-1 puts the vertex
 //               into the owner's F_{t+1}.
 // A hierarchical barrier after each exchange also sums |F_t| and the edges
-// removed.  A degree >= 255 lives in the global degree array instead (marked
-// 255 in LDS) and is updated with device atomics.
+// removed.  A degree >= 15 lives in the global degree array instead (marked
+// 15 in LDS) and is updated with device atomics; a round >= 15 is written to
+// vertex_round or edge_round at once (also marked 15).  The other rounds and
+// degrees are written in order at the end.
 //
 // Global engine (used when a workgroup's vertex or edge range does not fit in
 // LDS, or the team is too small).  Every round, the threads walk F_t and claim
@@ -57,7 +59,7 @@ constexpr int kDenseItems = 8;          // vertices per thread in the dense pass
 constexpr int kDenseTile = kBlock * kDenseItems;
 
 constexpr int kOT = 1024;             // threads per owner workgroup
-constexpr uint32_t kOwnMaxV = 98304;  // owned vertices (LDS degree bytes)
+constexpr uint32_t kOwnMaxV = 98304;  // owned vertices (LDS degree nibbles)
 constexpr uint32_t kOwnMaxE = 65536;  // owned edges (LDS alive and claimed bits)
 constexpr uint32_t kOwnMaxT = 1024;   // owner workgroups (LDS per-destination counters)
 constexpr uint64_t kDenseRatio = 3;   // dense round when |F_{t-1}| * 3 >= alive edges
