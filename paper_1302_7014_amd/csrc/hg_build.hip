@@ -48,6 +48,10 @@ constexpr int kRowsU = 4;                       // edge rows per thread in fligh
 constexpr uint32_t kSortPairs = 8192;           // pairs sorted in LDS per scatter chunk
 constexpr int kPairsU = 4;                      // pairs per thread in flight in the bucket build
 constexpr uint32_t kNone = ~0u;
+constexpr uint32_t kSort4 = 16384;              // 4-byte pairs sorted in LDS per flat-scatter chunk
+constexpr uint32_t kMaxB4 = 2048;               // buckets of the flat scatter (n <= 2^24)
+constexpr uint32_t kMaxTiles4 = 1024;           // tiles of the flat scatter (m <= 2^24)
+constexpr uint32_t kBlk = 32;                   // places per entry of the bucket build's tile table
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 __device__ inline uint64_t ceil_div_dev(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -268,6 +272,78 @@ __global__ void __launch_bounds__(kBT)
   }
 }
 
+// Up to 2048 buckets and 2048 tiles (n <= 2^24): each tile writes its pairs
+// straight to their (bucket, tile) runs, whose starts are the scanned hist8,
+// as 4-byte pairs (edge - e0) << kBinShift | (vertex - first vertex of the
+// bucket), with e0 the tile's first edge.  kSort4 pairs at a time are ranked
+// per bucket and sorted in LDS, then stored in sorted order, so neighbouring
+// lanes store to neighbouring addresses within each run.
+template <int R>
+__global__ void __launch_bounds__(kBT)
+    k_bin_scatter4(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nb,
+                   uint64_t ntiles, const uint32_t *__restrict__ hist8, uint32_t *pairs) {
+  constexpr int kEPT = (kSort4 / kBT) / R;            // edges per thread per chunk
+  constexpr uint32_t kCE = (uint32_t)kEPT * kBT;      // edges per chunk: <= kSort4 pairs
+  static_assert(kCE * R <= kSort4, "a chunk's pairs fit in LDS");
+  __shared__ uint32_t sp[kSort4];
+  __shared__ uint16_t sb[kSort4];   // the bucket of each sorted pair
+  __shared__ uint32_t cur[kMaxB4];  // next place of this tile in each bucket
+  __shared__ uint32_t cnt[kMaxB4];  // this chunk's pairs per bucket
+  __shared__ uint32_t st[kMaxB4];   // their exclusive scan
+  __shared__ uint32_t lds[kBT / kWave + 1];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t b = tid; b < nb; b += kBT) cur[b] = hist8[(uint64_t)b * ntiles + blockIdx.x];
+  const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
+  const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
+  for (uint64_t c0 = e0; c0 < e1; c0 += kCE) {
+    const uint64_t c1 = c0 + kCE < e1 ? c0 + kCE : e1;
+    for (uint32_t b = tid; b < nb; b += kBT) cnt[b] = 0;
+    __syncthreads();
+    uint32_t ids[kEPT][R], rk[kEPT][R];
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+      const uint64_t e = c0 + (uint64_t)u * kBT + tid;
+#pragma unroll
+      for (int j = 0; j < R; ++j) ids[u][j] = e < c1 ? edges[e * R + j] : kNone;
+    }
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u)
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if (ids[u][j] < n) rk[u][j] = atomicAdd(&cnt[ids[u][j] >> kBinShift], 1u);
+    __syncthreads();
+    // exclusive scan of cnt[0..nb), two buckets per thread
+    const uint32_t b2 = 2 * tid;
+    const uint32_t x0 = b2 < nb ? cnt[b2] : 0u, x1 = b2 + 1 < nb ? cnt[b2 + 1] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<kBT>(x0 + x1, &tot, lds);
+    if (b2 < nb) st[b2] = ex;
+    if (b2 + 1 < nb) st[b2 + 1] = ex + x0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kEPT; ++u) {
+      const uint32_t el = static_cast<uint32_t>(c0 - e0) + (uint32_t)u * kBT + tid;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint32_t v = ids[u][j];
+        if (v < n) {
+          const uint32_t b = v >> kBinShift;
+          const uint32_t i = st[b] + rk[u][j];
+          sp[i] = (el << kBinShift) | (v & (uint32_t)(kBinV - 1));
+          sb[i] = static_cast<uint16_t>(b);
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < tot; i += kBT) {
+      const uint32_t b = sb[i];
+      pairs[cur[b] + (i - st[b])] = sp[i];
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < nb; b += kBT) cur[b] += cnt[b];
+  }
+}
+
 // One workgroup per (super-bucket sb, group of kSplitTiles tiles): the pairs of
 // those tiles in sb's slice of pairs_in go to their (bucket, tile) runs in
 // pairs_out, whose starts are the scanned hist8.  A pair's tile is its edge id's.
@@ -308,12 +384,20 @@ __global__ void __launch_bounds__(kBT)
 }
 
 // One workgroup per bucket: degrees, offsets and edge lists of its vertices.
+// P = uint64_t: pairs are (edge << 32 | vertex).  P = uint32_t: pairs are
+// (edge - first edge of its tile) << kBinShift | (vertex - first vertex of the
+// bucket), and the bucket's runs are in tile order, so a pair's tile is the
+// last tile whose run starts at or before the pair's place.
+template <typename P>
 __global__ void __launch_bounds__(kBT)
-    k_bin_build(const uint64_t *__restrict__ pairs, uint32_t n, uint32_t nb, uint64_t ntiles,
+    k_bin_build(const P *__restrict__ pairs, uint32_t n, uint32_t nb, uint64_t ntiles,
                 const uint32_t *__restrict__ hist8, const uint32_t *total, uint32_t *offsets,
                 uint32_t *inc, uint32_t *deg, uint32_t *pmax) {
+  constexpr bool kP4 = sizeof(P) == 4;
   __shared__ uint32_t cnt[kBinV + kBinV / 32];
   __shared__ uint32_t stage[kStageCap];
+  __shared__ uint32_t bnd[kP4 ? kMaxTiles4 + 1 : 1];           // start of each tile's run
+  __shared__ uint16_t blk[kP4 ? kStageCap / kBlk : 1];         // tile of every kBlk-th place
   __shared__ uint32_t lds[kBT / kWave + 1];
   const uint32_t b = blockIdx.x;
   const uint32_t base = hist8[(uint64_t)b * ntiles];
@@ -321,17 +405,53 @@ __global__ void __launch_bounds__(kBT)
   const uint32_t v0 = b << kBinShift;
   const uint32_t nv = (n - v0) < (uint32_t)kBinV ? (n - v0) : (uint32_t)kBinV;
   for (uint32_t i = threadIdx.x; i < (uint32_t)(kBinV + kBinV / 32); i += kBT) cnt[i] = 0;
+  if (kP4) {
+    for (uint32_t t = threadIdx.x; t < (uint32_t)ntiles; t += kBT) bnd[t] = hist8[(uint64_t)b * ntiles + t];
+    if (threadIdx.x == 0) bnd[ntiles] = end;
+  }
   __syncthreads();
+  // the last tile whose run starts at or before place p (p in [base, end))
+  auto tile_search = [&](uint32_t p) -> uint32_t {
+    uint32_t lo = 0, hi = static_cast<uint32_t>(ntiles);
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (bnd[mid] <= p) lo = mid; else hi = mid;
+    }
+    return lo;
+  };
+  const bool staged = end - base <= kStageCap;
+  if (kP4 && staged) {
+    for (uint32_t j = threadIdx.x; j * kBlk < end - base; j += kBT)
+      blk[j] = static_cast<uint16_t>(tile_search(base + j * kBlk));
+  }
+  auto vloc = [&](P x) -> uint32_t {
+    if constexpr (kP4) return x & (uint32_t)(kBinV - 1);
+    else return static_cast<uint32_t>(x) - v0;
+  };
+  auto edge = [&](uint32_t p, P x) -> uint32_t {
+    if constexpr (kP4) {
+      uint32_t t;
+      if (staged) {
+        t = blk[(p - base) / kBlk];
+        while (bnd[t + 1] <= p) ++t;
+      } else {
+        t = tile_search(p);
+      }
+      return t * static_cast<uint32_t>(kTileEdges) + (x >> kBinShift);
+    } else {
+      return static_cast<uint32_t>(x >> 32);
+    }
+  };
   for (uint32_t p0 = base + threadIdx.x; p0 < end; p0 += kPairsU * kBT) {
     uint32_t vs[kPairsU];
 #pragma unroll
     for (int u = 0; u < kPairsU; ++u) {
       const uint32_t p = p0 + u * kBT;
-      vs[u] = p < end ? static_cast<uint32_t>(pairs[p]) : kNone;
+      vs[u] = p < end ? vloc(pairs[p]) : kNone;
     }
 #pragma unroll
     for (int u = 0; u < kPairsU; ++u)
-      if (vs[u] != kNone) atomicAdd(&cnt[pad(vs[u] - v0)], 1u);
+      if (vs[u] != kNone) atomicAdd(&cnt[pad(vs[u])], 1u);
   }
   __syncthreads();
   // exclusive scan of cnt[0..kBinV): kPer consecutive counts per thread
@@ -362,28 +482,29 @@ __global__ void __launch_bounds__(kBT)
   }
   __syncthreads();
   const uint32_t total_b = end - base;
-  if (total_b <= kStageCap) {
+  if (staged) {
     for (uint32_t p0 = base + threadIdx.x; p0 < end; p0 += kPairsU * kBT) {
-      uint64_t pr[kPairsU];
+      P pr[kPairsU];
 #pragma unroll
       for (int u = 0; u < kPairsU; ++u) {
         const uint32_t p = p0 + u * kBT;
-        pr[u] = p < end ? pairs[p] : ~0ull;
+        pr[u] = p < end ? pairs[p] : P(0);
       }
 #pragma unroll
       for (int u = 0; u < kPairsU; ++u) {
-        if (p0 + u * kBT >= end) continue;
-        const uint32_t pos = atomicAdd(&cnt[pad(static_cast<uint32_t>(pr[u]) - v0)], 1u);
-        stage[pos] = static_cast<uint32_t>(pr[u] >> 32);
+        const uint32_t p = p0 + u * kBT;
+        if (p >= end) continue;
+        const uint32_t pos = atomicAdd(&cnt[pad(vloc(pr[u]))], 1u);
+        stage[pos] = edge(p, pr[u]);
       }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < total_b; i += kBT) inc[base + i] = stage[i];
   } else {
     for (uint32_t p = base + threadIdx.x; p < end; p += kBT) {
-      const uint64_t pr = pairs[p];
-      const uint32_t pos = atomicAdd(&cnt[pad(static_cast<uint32_t>(pr) - v0)], 1u);
-      inc[base + pos] = static_cast<uint32_t>(pr >> 32);
+      const P pr = pairs[p];
+      const uint32_t pos = atomicAdd(&cnt[pad(vloc(pr))], 1u);
+      inc[base + pos] = edge(p, pr);
     }
   }
 }
@@ -469,6 +590,21 @@ peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t
   uint32_t *pmax = c.take<uint32_t>(z.nb + 4);
   uint32_t *total = pmax + z.nb;      // pairs, from the super-bucket scan
   uint32_t *total8 = pmax + z.nb + 1; // the same, from the bucket scan
+  const bool flat = z.ntiles && z.nb <= kMaxB4 && z.ntiles <= kMaxTiles4;
+  if (flat) {
+    // two levels: tiles to (bucket, tile) runs of 4-byte pairs, then buckets
+    hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
+                       (uint32_t)z.nb, (uint32_t)z.nsb, z.ntiles, hist, hist8, info);
+    scan_u32(hist8, z.hist8, hist8, nullptr, part8, nullptr, total8, nullptr, s);
+    uint32_t *pairs4 = reinterpret_cast<uint32_t *>(pairs);
+    hipLaunchKernelGGL(k_bin_scatter4<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
+                       (uint32_t)z.nb, z.ntiles, hist8, pairs4);
+    hipLaunchKernelGGL(k_bin_build<uint32_t>, dim3(z.nb), dim3(kBT), 0, s, pairs4, n,
+                       (uint32_t)z.nb, z.ntiles, hist8, total8, offsets, inc, deg, pmax);
+    hipLaunchKernelGGL(k_max_u32, dim3(1), dim3(kBlock), 0, s, pmax, z.nb, info + 1);
+    PEEL_HIP_TRY(hipGetLastError());
+    return PEEL_OK;
+  }
   if (z.ntiles) {
     hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
                        (uint32_t)z.nb, (uint32_t)z.nsb, z.ntiles, hist, hist8, info);
@@ -485,7 +621,7 @@ peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t
                        hist8, z.nb, 0u);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(kBlock), 0, s, total8, (uint64_t)1, 0u);
   }
-  hipLaunchKernelGGL(k_bin_build, dim3(z.nb), dim3(kBT), 0, s, pairs2, n, (uint32_t)z.nb,
+  hipLaunchKernelGGL(k_bin_build<uint64_t>, dim3(z.nb), dim3(kBT), 0, s, pairs2, n, (uint32_t)z.nb,
                      z.ntiles ? z.ntiles : 1, hist8, total8, offsets, inc, deg, pmax);
   hipLaunchKernelGGL(k_max_u32, dim3(1), dim3(kBlock), 0, s, pmax, z.nb, info + 1);
   PEEL_HIP_TRY(hipGetLastError());
