@@ -27,9 +27,10 @@ def _check_csr(n, edges, res):
     off = host_u32(res["csr"].offsets)[: n + 1].astype(np.int64)
     assert off[0] == 0 and np.array_equal(np.diff(off), deg)
     inc = host_u32(res["csr"].inc)[: m * r].astype(np.int64)
-    # each vertex's list is the multiset of edges that hold it
-    want = np.repeat(np.arange(m), r)[np.argsort(edges.ravel(), kind="stable")]
-    got = np.concatenate([np.sort(inc[off[v]:off[v + 1]]) for v in range(n)]) if m else inc
+    # each vertex's list is the multiset of edges that hold it: compare the
+    # sorted (vertex, edge) keys of the lists with those of the edge rows
+    got = np.sort(np.repeat(np.arange(n, dtype=np.int64), deg) * max(m, 1) + inc)
+    want = np.sort(edges.ravel().astype(np.int64) * max(m, 1) + np.repeat(np.arange(m), r))
     assert np.array_equal(got, want)
     assert res["info"][0] == 0 and res["info"][1] == (deg.max() if n else 0)
 
@@ -97,6 +98,23 @@ def test_degenerate_inputs(rounds):
         res = gpu_peel(n, e, k)
         _check_csr(n, e, res)
         _check_against_oracle(n, e, k, res)
+
+
+@pytest.mark.parametrize("which", ["n", "m"])
+def test_build_three_level_path(which):
+    # just past the two-level build's limits (2048 buckets of 8192 vertices,
+    # 1024 tiles of 16384 edges): the three-level build with 8-byte pairs runs
+    need_gpu()
+    if which == "n":
+        n, m, r, k = (1 << 24) + 4099, 300000, 3, 2
+    else:
+        n, m, r, k = 1 << 20, (1 << 24) + 777, 2, 22  # 7 rounds, a large 22-core
+    e = gen.gnm_edges(n, m, r, 41)
+    say("three-level build", n, m, r)
+    res = gpu_peel(n, e, k)
+    assert res["flags"] == 0
+    _check_csr(n, e, res)
+    _check_against_oracle(n, e, k, res)
 
 
 def test_config_kcore_small_seeds():
