@@ -442,17 +442,49 @@ __global__ void __launch_bounds__(kBT)
       return static_cast<uint32_t>(x >> 32);
     }
   };
-  for (uint32_t p0 = base + threadIdx.x; p0 < end; p0 += kPairsU * kBT) {
-    uint32_t vs[kPairsU];
+  // f(place, pair) for every pair of [base, end), kPairsU loads per thread in
+  // flight.  4-byte pairs are read 16 bytes at a time; the pair buffer is sized
+  // for 8-byte pairs, so the vector holding the last pair stays inside it.
+  auto for_pairs = [&](auto f) {
+    if constexpr (kP4) {
+      const uint4 *p4 = reinterpret_cast<const uint4 *>(pairs);
+      const uint32_t q_lo = base / 4, q_hi = (end + 3) / 4;
+      for (uint32_t q0 = q_lo + threadIdx.x; q0 < q_hi; q0 += kPairsU * kBT) {
+        uint4 x[kPairsU];
 #pragma unroll
-    for (int u = 0; u < kPairsU; ++u) {
-      const uint32_t p = p0 + u * kBT;
-      vs[u] = p < end ? vloc(pairs[p]) : kNone;
+        for (int u = 0; u < kPairsU; ++u) {
+          const uint32_t q = q0 + u * kBT;
+          if (q < q_hi) x[u] = p4[q];
+        }
+#pragma unroll
+        for (int u = 0; u < kPairsU; ++u) {
+          const uint32_t q = q0 + u * kBT;
+          if (q >= q_hi) continue;
+          const uint32_t w[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint32_t p = 4 * q + c;
+            if (p >= base && p < end) f(p, w[c]);
+          }
+        }
+      }
+    } else {
+      for (uint32_t p0 = base + threadIdx.x; p0 < end; p0 += kPairsU * kBT) {
+        P pr[kPairsU];
+#pragma unroll
+        for (int u = 0; u < kPairsU; ++u) {
+          const uint32_t p = p0 + u * kBT;
+          pr[u] = p < end ? pairs[p] : P(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kPairsU; ++u) {
+          const uint32_t p = p0 + u * kBT;
+          if (p < end) f(p, pr[u]);
+        }
+      }
     }
-#pragma unroll
-    for (int u = 0; u < kPairsU; ++u)
-      if (vs[u] != kNone) atomicAdd(&cnt[pad(vs[u])], 1u);
-  }
+  };
+  for_pairs([&](uint32_t, P x) { atomicAdd(&cnt[pad(vloc(x))], 1u); });
   __syncthreads();
   // exclusive scan of cnt[0..kBinV): kPer consecutive counts per thread
   constexpr int kPer = kBinV / kBT;
@@ -483,21 +515,10 @@ __global__ void __launch_bounds__(kBT)
   __syncthreads();
   const uint32_t total_b = end - base;
   if (staged) {
-    for (uint32_t p0 = base + threadIdx.x; p0 < end; p0 += kPairsU * kBT) {
-      P pr[kPairsU];
-#pragma unroll
-      for (int u = 0; u < kPairsU; ++u) {
-        const uint32_t p = p0 + u * kBT;
-        pr[u] = p < end ? pairs[p] : P(0);
-      }
-#pragma unroll
-      for (int u = 0; u < kPairsU; ++u) {
-        const uint32_t p = p0 + u * kBT;
-        if (p >= end) continue;
-        const uint32_t pos = atomicAdd(&cnt[pad(vloc(pr[u]))], 1u);
-        stage[pos] = edge(p, pr[u]);
-      }
-    }
+    for_pairs([&](uint32_t p, P x) {
+      const uint32_t pos = atomicAdd(&cnt[pad(vloc(x))], 1u);
+      stage[pos] = edge(p, x);
+    });
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < total_b; i += kBT) inc[base + i] = stage[i];
   } else {
