@@ -65,6 +65,8 @@ constexpr uint32_t kOwnMaxT = 1024;   // owner workgroups (LDS per-destination c
 constexpr uint64_t kDenseRatio = 3;   // dense round when |F_{t-1}| * 3 >= alive edges
 constexpr uint32_t kNoVertex = 0xffffffffu;
 constexpr uint32_t kNib = 15;         // escape value of the owner engine's 4-bit fields
+constexpr int kSendU = 4;             // messages per thread in one sorted send chunk
+constexpr uint32_t kSendChunk = kSendU * kOT;  // messages sorted in LDS at a time
 constexpr int kLU = 4;                // queue entries per thread whose loads are in flight
 
 enum : uint32_t { kModeUndecided = 0, kModeOwnerDone = 1, kModeGlobal = 2 };
@@ -162,6 +164,8 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   __shared__ uint32_t s_pre[kOT];
   __shared__ uint32_t scan_lds[kOT / kWave + 1];
   __shared__ uint32_t fbl[kOwnMaxV / 32];  // the next frontier, as bits over my vertices
+  __shared__ uint32_t sbuf[kSendChunk];    // messages sorted by destination before a send
+  __shared__ uint32_t sst[kOwnMaxT];       // their starts per destination
   __shared__ uint32_t s_n, s_w, s_p;
 
   PeelCtrl *ctrl = a.ctrl;
@@ -241,6 +245,45 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     else {
       atomicOr(&deg4[lv >> 3], kNib << sh);
       a.vr[v] = t;
+    }
+  };
+  // Sends the messages src[0, total) below `lim` to the queues q, at cur[d]
+  // onwards for destination d = x / per (cur[] already reserved; it advances).
+  // kSendChunk messages at a time are ranked per destination, sorted in LDS
+  // and stored in sorted order, so neighbouring lanes store to neighbouring
+  // places of one destination's run instead of one store per destination.
+  // Uses cnt[] (free once cur[] is set).  Every thread calls it.
+  auto sorted_send = [&](const uint32_t *src, uint32_t total, uint32_t lim, uint32_t per,
+                         uint32_t T_, uint32_t *q) {
+    for (uint32_t c0 = 0; c0 < total; c0 += kSendChunk) {
+      const uint32_t cn = total - c0 < kSendChunk ? total - c0 : kSendChunk;
+      for (uint32_t d = tid; d < T_; d += kOT) cnt[d] = 0;
+      __syncthreads();
+      uint32_t x[kSendU], rk[kSendU];
+#pragma unroll
+      for (int u = 0; u < kSendU; ++u) {
+        const uint32_t i = (uint32_t)u * kOT + tid;
+        x[u] = i < cn ? src[c0 + i] : lim;
+      }
+#pragma unroll
+      for (int u = 0; u < kSendU; ++u)
+        if (x[u] < lim) rk[u] = atomicAdd(&cnt[x[u] / per], 1u);
+      __syncthreads();
+      uint32_t tot;
+      const uint32_t ex = block_exclusive_scan<kOT>(tid < T_ ? cnt[tid] : 0u, &tot, scan_lds);
+      if (tid < T_) sst[tid] = ex;
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kSendU; ++u)
+        if (x[u] < lim) sbuf[sst[x[u] / per] + rk[u]] = x[u];
+      __syncthreads();
+      for (uint32_t i = tid; i < tot; i += kOT) {
+        const uint32_t v = sbuf[i];
+        const uint32_t d = v / per;
+        q[cur[d] + (i - sst[d])] = v;
+      }
+      __syncthreads();
+      for (uint32_t d = tid; d < T_; d += kOT) cur[d] += cnt[d];
     }
   };
   // my edge le dies in round t (its nibble is 0 until now)
@@ -396,17 +439,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         cur[d] = c ? d * Eb * R + atomicAdd(&ctrl->qh_claim[d], c) : 0u;
       }
       __syncthreads();
-      for (uint32_t i0 = tid; i0 < nc; i0 += kLU * kOT) {
-        uint32_t e[kLU];
-#pragma unroll
-        for (int u = 0; u < kLU; ++u) {
-          const uint32_t i = i0 + u * kOT;
-          e[u] = i < nc ? claims[i] : kNoVertex;
-        }
-#pragma unroll
-        for (int u = 0; u < kLU; ++u)
-          if (e[u] != kNoVertex) a.qclaim[atomicAdd(&cur[e[u] / Eb], 1u)] = e[u];
-      }
+      sorted_send(claims, nc, (uint32_t)m, Eb, T, a.qclaim);
     }
     // The barrier sums |F_t| and, in subtables mode, the waiting bits (high word).
     pend -= sub ? fcnt : 0u;
@@ -436,7 +469,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
     __syncthreads();
     if (dense) {
-      constexpr int kOU = R <= 4 ? 4 : 2;  // edges per thread whose loads are in flight
+      constexpr int kOU = 2;  // edges per thread whose loads are in flight
       // Scan my alive edges in order (coalesced rows), kOU per thread at a time
       // so that their loads overlap.  A dying edge's slots in F_t are replaced
       // by kNoVertex in the staged row: those vertices are already at degree 0.
@@ -586,17 +619,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       cur[d] = c ? a.offsets[dv] + atomicAdd(&ctrl->qh_dec[d], c) : 0u;
     }
     __syncthreads();
-    for (uint32_t i0 = tid; i0 < won * R; i0 += kLU * kOT) {
-      uint32_t x[kLU];
-#pragma unroll
-      for (int u = 0; u < kLU; ++u) {
-        const uint32_t i = i0 + u * kOT;
-        x[u] = i < won * R ? myStage[i] : kNoVertex;
-      }
-#pragma unroll
-      for (int u = 0; u < kLU; ++u)
-        if (x[u] < n) a.qdec[atomicAdd(&cur[x[u] / Vb], 1u)] = x[u];
-    }
+    sorted_send(myStage, won * R, n, Vb, T, a.qdec);
     uint64_t et;
     if (!sum_barrier(&ctrl->bar, T, slot, won, &epoch, a.limit, &et, ctrl->stamp)) return;
     if (slot == 0 && tid == 0) a.stats[2ull * (t - 1) + 1] = et;
