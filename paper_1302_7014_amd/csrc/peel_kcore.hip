@@ -252,9 +252,17 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   // kSendChunk messages at a time are ranked per destination, sorted in LDS
   // and stored in sorted order, so neighbouring lanes store to neighbouring
   // places of one destination's run instead of one store per destination.
-  // Uses cnt[] (free once cur[] is set).  Every thread calls it.
+  // Uses cnt[] (free once cur[] is set).  Every thread calls it; `total` is
+  // the same in every thread.
   auto sorted_send = [&](const uint32_t *src, uint32_t total, uint32_t lim, uint32_t per,
                          uint32_t T_, uint32_t *q) {
+    if (total <= (uint32_t)kOT) {
+      // a few messages (the many small rounds near and above the threshold):
+      // sorting would cost more than the stores it merges
+      const uint32_t x = tid < total ? src[tid] : lim;
+      if (x < lim) q[atomicAdd(&cur[x / per], 1u)] = x;
+      return;
+    }
     for (uint32_t c0 = 0; c0 < total; c0 += kSendChunk) {
       const uint32_t cn = total - c0 < kSendChunk ? total - c0 : kSendChunk;
       for (uint32_t d = tid; d < T_; d += kOT) cnt[d] = 0;
@@ -469,7 +477,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
     __syncthreads();
     if (dense) {
-      constexpr int kOU = 2;  // edges per thread whose loads are in flight
+      constexpr int kOU = R <= 4 ? 2 : 1;  // edges per thread whose loads are in flight
       // Scan my alive edges in order (coalesced rows), kOU per thread at a time
       // so that their loads overlap.  A dying edge's slots in F_t are replaced
       // by kNoVertex in the staged row: those vertices are already at degree 0.
