@@ -28,6 +28,19 @@ __host__ __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t i) {
 __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
 // ---------------------------------------------------------------------------
+// Blocks are dispatched to the GPU's 8 XCDs round robin (block b runs on XCD
+// b % 8).  For a grid of `count` blocks, one per item, this maps block b to an
+// item so that each XCD takes a contiguous range of items: neighbouring items,
+// whose outputs share cache lines, then go through one XCD's L2.  A bijection
+// on [0, count) whatever the dispatch order, so only speed depends on it.
+constexpr uint32_t kXcds = 8;
+__device__ inline uint32_t xcd_item(uint32_t b, uint32_t count) {
+  const uint32_t x = b % kXcds, i = b / kXcds;
+  const uint32_t q = count / kXcds, rem = count % kXcds;
+  return x * q + (x < rem ? x : rem) + i;
+}
+
+// ---------------------------------------------------------------------------
 // Wave / block prefix sums.
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }

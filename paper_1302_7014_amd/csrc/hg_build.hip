@@ -177,7 +177,8 @@ __global__ void __launch_bounds__(kBT)
   __shared__ uint32_t h[kMaxSuper * kSubPer];
   for (uint32_t b = threadIdx.x; b < nsb * kSubPer; b += kBT) h[b] = 0;
   __syncthreads();
-  const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
+  const uint32_t tile = xcd_item(blockIdx.x, static_cast<uint32_t>(ntiles));
+  const uint64_t e0 = (uint64_t)tile * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
   bool bad = false;
   for (uint64_t eb = e0 + threadIdx.x; eb < e1; eb += kRowsU * kBT) {
@@ -203,12 +204,12 @@ __global__ void __launch_bounds__(kBT)
   }
   if (bad) atomicOr(&info[0], PEEL_FLAG_ERANGE);
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb; b += kBT) hist8[(uint64_t)b * ntiles + blockIdx.x] = h[b];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBT) hist8[(uint64_t)b * ntiles + tile] = h[b];
   for (uint32_t sb = threadIdx.x; sb < nsb; sb += kBT) {
     uint32_t c = 0;
 #pragma unroll
     for (int q = 0; q < kSubPer; ++q) c += h[sb * kSubPer + q];
-    hist[(uint64_t)sb * ntiles + blockIdx.x] = c;
+    hist[(uint64_t)sb * ntiles + tile] = c;
   }
 }
 
@@ -228,8 +229,9 @@ __global__ void __launch_bounds__(kBT)
   __shared__ uint32_t st[kMaxSuper];   // their exclusive scan
   __shared__ uint32_t lds[kBT / kWave + 1];
   const uint32_t tid = threadIdx.x;
-  for (uint32_t b = tid; b < nsb; b += kBT) cur[b] = hist[(uint64_t)b * ntiles + blockIdx.x];
-  const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
+  const uint32_t tile = xcd_item(blockIdx.x, static_cast<uint32_t>(ntiles));
+  for (uint32_t b = tid; b < nsb; b += kBT) cur[b] = hist[(uint64_t)b * ntiles + tile];
+  const uint64_t e0 = (uint64_t)tile * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
   for (uint64_t c0 = e0; c0 < e1; c0 += kCE) {
     const uint64_t c1 = c0 + kCE < e1 ? c0 + kCE : e1;
@@ -292,8 +294,9 @@ __global__ void __launch_bounds__(kBT)
   __shared__ uint32_t st[kMaxB4];   // their exclusive scan
   __shared__ uint32_t lds[kBT / kWave + 1];
   const uint32_t tid = threadIdx.x;
-  for (uint32_t b = tid; b < nb; b += kBT) cur[b] = hist8[(uint64_t)b * ntiles + blockIdx.x];
-  const uint64_t e0 = (uint64_t)blockIdx.x * kTileEdges;
+  const uint32_t tile = xcd_item(blockIdx.x, static_cast<uint32_t>(ntiles));
+  for (uint32_t b = tid; b < nb; b += kBT) cur[b] = hist8[(uint64_t)b * ntiles + tile];
+  const uint64_t e0 = (uint64_t)tile * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
   for (uint64_t c0 = e0; c0 < e1; c0 += kCE) {
     const uint64_t c1 = c0 + kCE < e1 ? c0 + kCE : e1;
@@ -399,7 +402,7 @@ __global__ void __launch_bounds__(kBT)
   __shared__ uint32_t bnd[kP4 ? kMaxTiles4 + 1 : 1];           // start of each tile's run
   __shared__ uint16_t blk[kP4 ? kStageCap / kBlk : 1];         // tile of every kBlk-th place
   __shared__ uint32_t lds[kBT / kWave + 1];
-  const uint32_t b = blockIdx.x;
+  const uint32_t b = xcd_item(blockIdx.x, nb);
   const uint32_t base = hist8[(uint64_t)b * ntiles];
   const uint32_t end = (b + 1 < nb) ? hist8[(uint64_t)(b + 1) * ntiles] : *total;
   const uint32_t v0 = b << kBinShift;
