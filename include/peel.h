@@ -202,6 +202,29 @@ peel_status iblt_delete(const iblt_desc *desc, iblt_cell *cells, const uint64_t 
                         uint64_t nkeys, void *stream);
 
 /*
+ * iblt_insert (sign = +1) or iblt_delete (sign = -1) computed another way, for
+ * large tables: the cells come out bit for bit as the per-key updates leave
+ * them (Section 5: each key's r cells take count += sign, key_sum ^= x,
+ * hash_sum ^= C(x), and these updates commute).  Instead of 3r device atomics
+ * per key into a table far larger than the caches, the keys are counting-
+ * sorted by block of cells and each block is updated once in LDS, so the
+ * table is read and written once, in order.  The reserved words of each cell
+ * are left as they were.
+ *
+ *   desc, cells, keys, nkeys   as for iblt_insert (cells 32-byte aligned).
+ *   sign                       +1 or -1; anything else is PEEL_EINVAL.
+ *   ws                         (device) ws_bytes >= iblt_update_workspace(desc,
+ *                              nkeys): the sorted entries (10 r bytes per key)
+ *                              and their counts.
+ *
+ * Tables of more than 2^24 cells, or r * nkeys >= 2^32, take the per-key
+ * atomic path instead (same result; the workspace is then not used).
+ */
+size_t iblt_update_workspace(const iblt_desc *desc, uint64_t nkeys);
+peel_status iblt_update(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
+                        uint64_t nkeys, int32_t sign, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * List the table by round-synchronous pure-cell peeling, consuming `cells`
  * in place.  Round t takes K_t = the keys of the cells that are pure at the
  * start of the round (each key once, however many of its cells are pure);

@@ -28,6 +28,7 @@ FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT = 0x1, 0x2, 
 # Every symbol include/peel.h declares.
 EXPORTS = ("peel_strerror", "peel_abi_version", "hg_build_workspace", "hg_build",
            "peel_kcore_workspace", "peel_kcore", "peel_kcore_subtables", "iblt_insert",
+           "iblt_update_workspace", "iblt_update",
            "iblt_delete", "iblt_list_workspace", "iblt_list", "iblt_list_subtables",
            "iblt_list_signed",
            "iblt_list_batched_workspace", "iblt_list_batched")
@@ -69,10 +70,14 @@ def lib() -> C.CDLL:
         L.iblt_list_subtables.argtypes = L.iblt_list.argtypes
         L.iblt_list_signed.argtypes = [C.POINTER(IbltDesc), P, P, P, u64, P, u32, P, P, sz, P]
         L.iblt_delete.argtypes = L.iblt_insert.argtypes
+        L.iblt_update_workspace.argtypes = [C.POINTER(IbltDesc), u64]
+        L.iblt_update_workspace.restype = sz
+        L.iblt_update.argtypes = [C.POINTER(IbltDesc), P, P, u64, C.c_int32, P, sz, P]
         L.iblt_list_batched_workspace.argtypes = [u32, u64]
         L.iblt_list_batched_workspace.restype = sz
         L.iblt_list_batched.argtypes = [P, u32, u64, u32, C.POINTER(BatchSchedule), P, sz, P]
         for f in ("hg_build", "peel_kcore", "peel_kcore_subtables", "iblt_insert", "iblt_delete",
+                  "iblt_update",
                   "iblt_list", "iblt_list_subtables", "iblt_list_signed", "iblt_list_batched"):
             getattr(L, f).restype = C.c_int32
         _lib = L
@@ -193,6 +198,20 @@ def iblt_delete(desc: IbltDesc, cells: torch.Tensor, keys: torch.Tensor, stream=
     """Delete ``keys`` from ``cells`` (count down, same XORs)."""
     _check(lib().iblt_delete(C.byref(desc), _ptr(cells), _ptr(keys), keys.numel(),
                              _stream(stream)), "iblt_delete")
+
+
+def iblt_update_workspace(desc: IbltDesc, nkeys: int) -> int:
+    return int(lib().iblt_update_workspace(C.byref(desc), nkeys))
+
+
+def iblt_update(desc: IbltDesc, cells: torch.Tensor, keys: torch.Tensor, sign: int = 1,
+                ws: torch.Tensor | None = None, stream=None) -> None:
+    """iblt_insert (sign=+1) or iblt_delete (sign=-1) by binning the keys per
+    block of cells: the same cells, without a device atomic per update."""
+    if ws is None:
+        ws = workspace(iblt_update_workspace(desc, keys.numel()), cells.device)
+    _check(lib().iblt_update(C.byref(desc), _ptr(cells), _ptr(keys), keys.numel(), sign, _ptr(ws),
+                             ws.numel(), _stream(stream)), "iblt_update")
 
 
 @dataclass

@@ -14,4 +14,4 @@ extern "C" const char *peel_strerror(peel_status s) {
   }
 }
 
-extern "C" int peel_abi_version(void) { return 6; }
+extern "C" int peel_abi_version(void) { return 7; }

@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "scan.hpp"
 #include "host.hpp"
 
 namespace peel {
@@ -109,6 +110,185 @@ __device__ inline void load_cell(const iblt_cell *cell, int32_t *cnt, uint64_t *
   *ks = (uint64_t)a.z | ((uint64_t)a.w << 32);
   *hs = (uint64_t)b.x | ((uint64_t)b.y << 32);
 }
+
+// ---------------------------------------------------------------------------
+// Binned update (iblt_update).  Every key makes r cell updates.  They are
+// counting-sorted by super-bucket of kUSuper cells: one entry per (key, cell),
+// the key in ekey and the cell's place in its super-bucket in eloc.  Then each
+// block of kUBlk cells is loaded into LDS, takes the entries of its
+// super-bucket whose place falls in the block with LDS atomics, and is written
+// back in order.  No device atomic per update: the table is read and written
+// once, and each super-bucket's entries, read by its kUPer blocks on one XCD,
+// come from L2 after the first.  Each cell hash is computed once per entry in
+// the count and the scatter, and the checksum once per entry in the apply.
+constexpr int kUSuperShift = 14;                  // 16384 cells per super-bucket
+constexpr int kUBlkShift = 12;                    // 4096 cells per apply block
+constexpr uint32_t kUBlk = 1u << kUBlkShift;
+constexpr uint32_t kUPer = 1u << (kUSuperShift - kUBlkShift);  // apply blocks per super-bucket
+constexpr uint32_t kUMaxSuper = 1024;             // up to 2^24 cells
+constexpr uint64_t kUTile = 8192;                 // keys per count/scatter tile
+constexpr uint32_t kUChunk = 8192;                // entries sorted in LDS per scatter chunk
+constexpr int kUT = 1024;                         // threads per workgroup
+
+// hist[s * ntiles + tile] = entries of the tile's keys in super-bucket s.
+template <int R>
+__global__ void __launch_bounds__(kUT)
+    k_upd_count(Hash h, const uint64_t *__restrict__ keys, uint64_t nkeys, uint32_t nsb,
+                uint32_t ntiles, uint32_t *hist) {
+  __shared__ uint32_t cnt[kUMaxSuper];
+  for (uint32_t b = threadIdx.x; b < nsb; b += kUT) cnt[b] = 0;
+  __syncthreads();
+  const uint32_t tile = xcd_item(blockIdx.x, ntiles);
+  const uint64_t k0 = (uint64_t)tile * kUTile;
+  const uint64_t k1 = k0 + kUTile < nkeys ? k0 + kUTile : nkeys;
+  constexpr int kU = 4;
+  for (uint64_t i0 = k0 + threadIdx.x; i0 < k1; i0 += kU * kUT) {
+    uint64_t x[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint64_t i = i0 + (uint64_t)u * kUT;
+      x[u] = i < k1 ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (i0 + (uint64_t)u * kUT >= k1) continue;
+#pragma unroll
+      for (int j = 0; j < R; ++j) atomicAdd(&cnt[cell_of(h, j, x[u]) >> kUSuperShift], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nsb; b += kUT) hist[(uint64_t)b * ntiles + tile] = cnt[b];
+}
+
+// Each tile writes its entries into its run of every super-bucket, whose
+// starts are the scanned hist.  kUChunk entries at a time are ranked per
+// super-bucket, sorted in LDS and stored in sorted order.
+template <int R>
+__global__ void __launch_bounds__(kUT)
+    k_upd_scatter(Hash h, const uint64_t *__restrict__ keys, uint64_t nkeys, uint32_t nsb,
+                  uint32_t ntiles, const uint32_t *__restrict__ hist, uint64_t *ekey,
+                  uint16_t *eloc) {
+  constexpr int kKPT = (int)(kUChunk / kUT) / R;      // keys per thread per chunk
+  constexpr uint32_t kCK = (uint32_t)kKPT * kUT;      // keys per chunk
+  static_assert(kKPT >= 1 && kCK * R <= kUChunk, "a chunk's entries fit in LDS");
+  __shared__ uint64_t sk[kUChunk];
+  __shared__ uint16_t sl[kUChunk];
+  __shared__ uint16_t ss[kUChunk];
+  __shared__ uint32_t cur[kUMaxSuper];
+  __shared__ uint32_t cnt[kUMaxSuper];
+  __shared__ uint32_t st[kUMaxSuper];
+  __shared__ uint32_t lds[kUT / kWave + 1];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t tile = xcd_item(blockIdx.x, ntiles);
+  for (uint32_t b = tid; b < nsb; b += kUT) cur[b] = hist[(uint64_t)b * ntiles + tile];
+  const uint64_t k0 = (uint64_t)tile * kUTile;
+  const uint64_t k1 = k0 + kUTile < nkeys ? k0 + kUTile : nkeys;
+  for (uint64_t c0 = k0; c0 < k1; c0 += kCK) {
+    for (uint32_t b = tid; b < nsb; b += kUT) cnt[b] = 0;
+    __syncthreads();
+    uint64_t x[kKPT];
+    uint32_t cl[kKPT][R], rk[kKPT][R];
+#pragma unroll
+    for (int u = 0; u < kKPT; ++u) {
+      const uint64_t i = c0 + (uint64_t)u * kUT + tid;
+      x[u] = i < k1 ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kKPT; ++u) {
+      if (c0 + (uint64_t)u * kUT + tid >= k1) continue;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        cl[u][j] = cell_of(h, j, x[u]);
+        rk[u][j] = atomicAdd(&cnt[cl[u][j] >> kUSuperShift], 1u);
+      }
+    }
+    __syncthreads();
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<kUT>(tid < nsb ? cnt[tid] : 0u, &tot, lds);
+    if (tid < nsb) st[tid] = ex;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kKPT; ++u) {
+      if (c0 + (uint64_t)u * kUT + tid >= k1) continue;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint32_t sb = cl[u][j] >> kUSuperShift;
+        const uint32_t i = st[sb] + rk[u][j];
+        sk[i] = x[u];
+        sl[i] = static_cast<uint16_t>(cl[u][j] & ((1u << kUSuperShift) - 1));
+        ss[i] = static_cast<uint16_t>(sb);
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < tot; i += kUT) {
+      const uint32_t b = ss[i];
+      const uint32_t o = cur[b] + (i - st[b]);
+      ekey[o] = sk[i];
+      eloc[o] = sl[i];
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < nsb; b += kUT) cur[b] += cnt[b];
+  }
+}
+
+// One workgroup per block of kUBlk cells (the kUPer blocks of a super-bucket
+// on one XCD): the cells in LDS, the super-bucket's entries whose place falls
+// in the block applied with LDS atomics, the cells written back.  The
+// reserved words are kept as they were.
+template <int R>
+__global__ void __launch_bounds__(kUT)
+    k_upd_apply(Hash h, iblt_cell *cells, uint64_t ncells, const uint64_t *__restrict__ ekey,
+                const uint16_t *__restrict__ eloc, const uint32_t *__restrict__ hist,
+                uint32_t nsb, uint32_t ntiles, const uint32_t *total, int32_t sign) {
+  __shared__ int32_t ccount[kUBlk];
+  __shared__ unsigned long long cks[kUBlk];
+  __shared__ unsigned long long chs[kUBlk];
+  const uint32_t item = xcd_item(blockIdx.x, nsb * kUPer);
+  const uint32_t sbi = item / kUPer, q = item % kUPer;
+  const uint64_t c_lo = ((uint64_t)sbi << kUSuperShift) + (uint64_t)q * kUBlk;
+  if (c_lo >= ncells) return;  // every thread of the block leaves
+  const uint32_t nc = ncells - c_lo < kUBlk ? static_cast<uint32_t>(ncells - c_lo) : kUBlk;
+  for (uint32_t i = threadIdx.x; i < nc; i += kUT) {
+    int32_t cn;
+    uint64_t ks, hs;
+    load_cell(cells + c_lo + i, &cn, &ks, &hs);
+    ccount[i] = cn;
+    cks[i] = ks;
+    chs[i] = hs;
+  }
+  __syncthreads();
+  const uint32_t lo = hist[(uint64_t)sbi * ntiles];
+  const uint32_t hi = sbi + 1 < nsb ? hist[(uint64_t)(sbi + 1) * ntiles] : *total;
+  constexpr int kU = 8;
+  for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += kU * kUT) {
+    uint32_t l[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t i = i0 + u * kUT;
+      l[u] = i < hi ? eloc[i] : 0xffffu;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if ((l[u] >> kUBlkShift) != q) continue;  // another block's cell, or past the end
+      const uint64_t x = ekey[i0 + u * kUT];
+      const uint32_t c = l[u] & (kUBlk - 1);
+      atomicAdd(&ccount[c], sign);
+      atomicXor(&cks[c], (unsigned long long)x);
+      atomicXor(&chs[c], (unsigned long long)check_of(h, x));
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nc; i += kUT) {
+    uint4 *p = reinterpret_cast<uint4 *>(cells + c_lo + i);
+    const uint4 a = p[0];
+    const uint4 b = p[1];
+    const uint64_t ks = cks[i], hs = chs[i];
+    p[0] = make_uint4(static_cast<uint32_t>(ccount[i]), a.y, static_cast<uint32_t>(ks),
+                      static_cast<uint32_t>(ks >> 32));
+    p[1] = make_uint4(static_cast<uint32_t>(hs), static_cast<uint32_t>(hs >> 32), b.z, b.w);
+  }
+}
+
 
 // True when cell c (already read as cnt/ks/hs) is pure and it is the owner of
 // its key: no cell of the key in a lower subtable is a pure cell of that key.
@@ -1013,12 +1193,95 @@ peel_status update_run(const iblt_desc *desc, iblt_cell *cells, const uint64_t *
   }
 }
 
+struct UpdSizes {
+  uint32_t nsb, ntiles;
+  uint64_t hist, entries;
+};
+
+UpdSizes upd_sizes(const iblt_desc *d, uint64_t nkeys) {
+  UpdSizes z{};
+  z.nsb = static_cast<uint32_t>((d->ncells + (1ull << kUSuperShift) - 1) >> kUSuperShift);
+  z.ntiles = static_cast<uint32_t>((nkeys + kUTile - 1) / kUTile);
+  z.hist = (uint64_t)z.nsb * (z.ntiles ? z.ntiles : 1);
+  z.entries = (uint64_t)d->r * nkeys;
+  return z;
+}
+
+// The binned update runs up to 2^24 cells and while entry places fit 32 bits.
+bool upd_binned(const iblt_desc *d, uint64_t nkeys) {
+  const UpdSizes z = upd_sizes(d, nkeys);
+  return nkeys > 0 && z.nsb <= kUMaxSuper && z.entries < (1ull << 32) && z.hist < (1ull << 32);
+}
+
+size_t upd_ws_bytes(const iblt_desc *d, uint64_t nkeys) {
+  if (!upd_binned(d, nkeys)) return 256;
+  const UpdSizes z = upd_sizes(d, nkeys);
+  return align_up(z.hist * 4) + align_up((scan_tiles(z.hist) + 1) * 4) + align_up(16) +
+         align_up(z.entries * 8) + align_up(z.entries * 2);
+}
+
+template <int R>
+peel_status launch_update_binned(const Hash &h, const iblt_desc *d, iblt_cell *cells,
+                                 const uint64_t *keys, uint64_t nkeys, int32_t sign, void *ws,
+                                 hipStream_t s) {
+  const UpdSizes z = upd_sizes(d, nkeys);
+  Carver c(ws);
+  uint32_t *hist = c.take<uint32_t>(z.hist);
+  uint32_t *part = c.take<uint32_t>(scan_tiles(z.hist) + 1);
+  uint32_t *total = c.take<uint32_t>(4);
+  uint64_t *ekey = c.take<uint64_t>(z.entries);
+  uint16_t *eloc = c.take<uint16_t>(z.entries);
+  hipLaunchKernelGGL(k_upd_count<R>, dim3(z.ntiles), dim3(kUT), 0, s, h, keys, nkeys, z.nsb,
+                     z.ntiles, hist);
+  scan_u32(hist, z.hist, hist, nullptr, part, nullptr, total, nullptr, s);
+  hipLaunchKernelGGL(k_upd_scatter<R>, dim3(z.ntiles), dim3(kUT), 0, s, h, keys, nkeys, z.nsb,
+                     z.ntiles, hist, ekey, eloc);
+  hipLaunchKernelGGL(k_upd_apply<R>, dim3(z.nsb * kUPer), dim3(kUT), 0, s, h, cells, d->ncells,
+                     ekey, eloc, hist, z.nsb, z.ntiles, total, sign);
+  PEEL_HIP_TRY(hipGetLastError());
+  return PEEL_OK;
+}
+
+peel_status update_binned_run(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
+                              uint64_t nkeys, int32_t sign, void *ws, size_t ws_bytes,
+                              void *stream) {
+  if (!desc_ok(desc) || !cells || (nkeys && !keys)) return PEEL_EINVAL;
+  if (reinterpret_cast<uintptr_t>(cells) % 32) return PEEL_EINVAL;
+  if (sign != 1 && sign != -1) return PEEL_EINVAL;
+  if (nkeys == 0) return PEEL_OK;
+  if (!upd_binned(desc, nkeys)) return update_run(desc, cells, keys, nkeys, stream, sign);
+  if (!ws) return PEEL_EINVAL;
+  if (ws_bytes < upd_ws_bytes(desc, nkeys)) return PEEL_ENOSPC;
+  const Hash h = make_hash(*desc);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  switch (desc->r) {
+    case 2: return launch_update_binned<2>(h, desc, cells, keys, nkeys, sign, ws, s);
+    case 3: return launch_update_binned<3>(h, desc, cells, keys, nkeys, sign, ws, s);
+    case 4: return launch_update_binned<4>(h, desc, cells, keys, nkeys, sign, ws, s);
+    case 5: return launch_update_binned<5>(h, desc, cells, keys, nkeys, sign, ws, s);
+    case 6: return launch_update_binned<6>(h, desc, cells, keys, nkeys, sign, ws, s);
+    case 7: return launch_update_binned<7>(h, desc, cells, keys, nkeys, sign, ws, s);
+    default: return launch_update_binned<8>(h, desc, cells, keys, nkeys, sign, ws, s);
+  }
+}
+
 }  // namespace
 }  // namespace peel
 
 extern "C" peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
                                    uint64_t nkeys, void *stream) {
   return update_run(desc, cells, keys, nkeys, stream, 1);
+}
+
+extern "C" size_t iblt_update_workspace(const iblt_desc *desc, uint64_t nkeys) {
+  if (!desc_ok(desc)) return 0;
+  return upd_ws_bytes(desc, nkeys);
+}
+
+extern "C" peel_status iblt_update(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
+                                   uint64_t nkeys, int32_t sign, void *ws, size_t ws_bytes,
+                                   void *stream) {
+  return update_binned_run(desc, cells, keys, nkeys, sign, ws, ws_bytes, stream);
 }
 
 extern "C" peel_status iblt_delete(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_version_and_strerror(L):
-    assert L.peel_abi_version() == 6
+    assert L.peel_abi_version() == 7
     for code in range(-6, 1):
         assert L.peel_strerror(code)
     assert L.peel_strerror(-99) == b"unknown status"
@@ -100,3 +100,22 @@ def test_oracle_and_library_share_no_code():
         if f.endswith((".py", ".c", ".h")):
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert not bad_orc.search(txt), f
+
+
+def test_binned_update_is_checked_on_the_host(L):
+    P = C.c_void_p
+    dummy = P(0x1000)
+    d = pk.iblt_desc(1 << 24, 3, 7)
+    # the sorted entries (10 bytes per key and subtable) dominate the workspace
+    nk = 10_296_982
+    assert L.iblt_update_workspace(C.byref(d), nk) >= 3 * nk * 10
+    big = pk.iblt_desc((1 << 24) + 1, 3, 7)  # past the binned limit: atomic path, no workspace
+    assert L.iblt_update_workspace(C.byref(big), nk) == 256
+    bad = pk.iblt_desc(2, 3, 7)
+    assert L.iblt_update_workspace(C.byref(bad), nk) == 0
+    for sign in (0, 2, -2):
+        assert L.iblt_update(C.byref(d), dummy, dummy, 5, sign, dummy, 1 << 30, None) == pk.binding.PEEL_EINVAL
+    assert L.iblt_update(C.byref(d), P(0x1010), dummy, 5, 1, dummy, 1 << 30, None) == pk.binding.PEEL_EINVAL
+    assert L.iblt_update(C.byref(d), dummy, dummy, nk, 1, None, 1 << 30, None) == pk.binding.PEEL_EINVAL
+    assert L.iblt_update(C.byref(d), dummy, dummy, nk, 1, dummy, 1024, None) == pk.binding.PEEL_ENOSPC
+    assert L.iblt_update(C.byref(d), dummy, dummy, 0, 1, None, 0, None) == pk.binding.PEEL_OK
