@@ -6,8 +6,9 @@ first served as arena space frees up, and runs the GPU as a pipeline:
 
 * admission: the request's table and buffers are carved from the arena, its
   keys are produced on the device by the caller's ``fill_keys`` and inserted
-  with ``iblt_insert`` on the insert stream (this stands for receiving the
-  table), overlapping whatever listing is running;
+  on the insert stream (this stands for receiving the table), overlapping
+  whatever listing is running: with ``iblt_insert``, or for a table of 2^18
+  cells and more (larger than an XCD's L2) with the binned ``iblt_update``;
 * listing, routed by table size: a table of more than ``small_cells`` cells is
   listed alone by ``iblt_list`` on one of ``large_lanes`` streams (taken in
   turn), as soon as its insert is done.  Each lane's runs use an equal share
@@ -124,6 +125,12 @@ class _Base:
         self.max_rounds = max_rounds
         self.keep_keys = keep_keys
         self.rejected = []
+        # tables from this size on (larger than an XCD's L2) are filled with the
+        # binned update; admissions run in order on one stream, so they share
+        # one workspace, grown as needed (outside the arena, like the list
+        # workspaces)
+        self.binned_min_cells = 1 << 18
+        self.upd_ws = None
 
     def _admit(self, q: Request, stream) -> bool:
         pieces = [32 * q.ncells, 8 * q.ncells, 8 * max(q.nkeys, 1), 8 * self.max_rounds, 64]
@@ -147,7 +154,17 @@ class _Base:
             cells.zero_()
             if q.nkeys:
                 self.fill_keys(q, ins[: q.nkeys])
-                pk.iblt_insert(desc, cells, ins[: q.nkeys], stream=stream)
+                if q.ncells >= self.binned_min_cells:
+                    need = pk.iblt_update_workspace(desc, q.nkeys)
+                    if self.upd_ws is None or self.upd_ws.numel() < need:
+                        torch.cuda.current_stream().wait_stream(stream)
+                        grown = 2 * self.upd_ws.numel() if self.upd_ws is not None else 0
+                        self.upd_ws = pk.workspace(max(need, grown), self.device)
+                        self.upd_ws.record_stream(stream)
+                        stream.wait_stream(torch.cuda.current_stream())
+                    pk.iblt_update(desc, cells, ins[: q.nkeys], 1, ws=self.upd_ws, stream=stream)
+                else:
+                    pk.iblt_insert(desc, cells, ins[: q.nkeys], stream=stream)
         q._table = pk.BatchTable(desc, cells, keys_out, stats, summ)
         return True
 

@@ -30,16 +30,24 @@ def _groups(q):
     return out
 
 
-def test_mix_equals_alone_and_oracle():
+@pytest.mark.parametrize("binned_min", [None, 1 << 10])
+def test_mix_equals_alone_and_oracle(binned_min):
+    # binned_min: tables from this size on are filled with the binned update
+    # (None: the server's default, which no table of this mix reaches)
     need_gpu()
     budget = 6 << 20  # small: arrivals must wait for space
     mix = _requests(80, 4000.0, 11)
-    say("serve mix", len(mix))
+    say("serve mix", len(mix), binned_min)
     srv = ContinuousServer(budget, _fill, max_cells=1 << 14, keep_keys=True)
+    fifo = FifoServer(budget, _fill, keep_keys=True, max_cells=1 << 14)
+    if binned_min is not None:
+        srv.binned_min_cells = fifo.binned_min_cells = binned_min
     done = srv.run(mix)
     assert len(done) == len(mix) and not srv.rejected
     assert srv.arena.peak <= budget and srv.batches >= 2 and srv.large >= 1
-    alone = FifoServer(budget, _fill, keep_keys=True, max_cells=1 << 14).run(_requests(80, 0.0, 11))
+    if binned_min is not None:
+        assert sum(q.ncells >= binned_min for q in mix) >= 20
+    alone = fifo.run(_requests(80, 0.0, 11))
     by_id = {q.rid: q for q in alone}
     for q in done:
         a = by_id[q.rid]
