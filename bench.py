@@ -233,8 +233,14 @@ def bench_signed(reps):
                            torch.empty(4096, dtype=torch.int64, device="cuda"),
                            torch.empty(8, dtype=torch.int64, device="cuda"))
     ws = pk.workspace(pk.iblt_list_workspace(d), "cuda")
-    tu, tl = Timer(), Timer()
+    wsu = pk.workspace(max(pk.iblt_update_workspace(d, na), pk.iblt_update_workspace(d, nb)), "cuda")
+    tu, tl, tb = Timer(), Timer(), Timer()
     for _ in range(reps + 2):
+        cells.zero_()
+        with tb:
+            pk.iblt_update(d, cells, a, 1, ws=wsu)
+            pk.iblt_update(d, cells, b, -1, ws=wsu)
+        tb.collect()
         cells.zero_()
         with tu:
             pk.iblt_insert(d, cells, a)
@@ -246,9 +252,10 @@ def bench_signed(reps):
     s = out.summary.cpu().numpy()
     lst = float(np.median(tl.ms[2:]))
     upd = float(np.median(tu.ms[2:]))
+    upd_b = float(np.median(tb.ms[2:]))
     return {"workload": "iblt_signed_r3_N16M_diff7M", "cells": N, "inserted": na, "deleted": nb,
             "difference": na + nb - 2 * no, "listed": int(s[0]), "rounds": int(s[1]),
-            "cells_left": int(s[2]), "update_ms": upd, "list_ms": lst,
+            "cells_left": int(s[2]), "update_ms": upd, "update_binned_ms": upd_b, "list_ms": lst,
             "list_keys_per_s": int(s[0]) / (lst * 1e-3)}
 
 
