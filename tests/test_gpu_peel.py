@@ -117,6 +117,32 @@ def test_build_three_level_path(which):
     _check_against_oracle(n, e, k, res)
 
 
+def test_global_engine_bit_exact(monkeypatch):
+    # the fallback engine (CAS claims and device-atomic degrees), which runs
+    # when a workgroup's vertex or edge range does not fit in LDS, forced here
+    need_gpu()
+    monkeypatch.setenv("PEEL_ENGINE", "global")
+    rng = np.random.default_rng(29)
+    for i in range(12):
+        r = int(rng.integers(2, 9))
+        k = int(rng.integers(1, 5))
+        n = int(rng.integers(r, 3000))
+        e = rng.integers(0, n, size=(int(rng.integers(0, 3 * n)), r)).astype(np.uint32)
+        say("global engine small", i, n, e.shape, k)
+        _check_against_oracle(n, e, k, gpu_peel(n, e, k))
+    n = (1 << 18) + 12345
+    for r, k, c in [(4, 2, 0.7), (4, 2, 0.85), (3, 3, 1.7)]:
+        e = gen.partitioned_edges(n, int(c * n), r, 23)
+        say("global engine medium", r, k, c)
+        _check_against_oracle(n, e, k, gpu_peel(n, e, k))
+    spec = configs.kcore_sweep(0.70)
+    e = spec.edges(1)
+    say("global engine", spec.name)
+    res = gpu_peel(spec.n, e, spec.k)
+    assert res["flags"] == 0
+    _check_against_oracle(spec.n, e, spec.k, res)
+
+
 def test_config_kcore_small_seeds():
     need_gpu()
     spec = configs.kcore_small()
