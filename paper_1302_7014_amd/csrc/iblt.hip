@@ -134,8 +134,9 @@ constexpr int kUT = 1024;                         // threads per workgroup
 template <int R>
 __global__ void __launch_bounds__(kUT)
     k_upd_count(Hash h, const uint64_t *__restrict__ keys, uint64_t nkeys, uint32_t nsb,
-                uint32_t ntiles, uint32_t *hist) {
+                uint32_t ntiles, uint32_t *hist, const unsigned long long *nkeys_dev) {
   __shared__ uint32_t cnt[kUMaxSuper];
+  if (nkeys_dev) nkeys = *nkeys_dev;  // the grid is sized for the most keys there can be
   for (uint32_t b = threadIdx.x; b < nsb; b += kUT) cnt[b] = 0;
   __syncthreads();
   const uint32_t tile = xcd_item(blockIdx.x, ntiles);
@@ -167,7 +168,8 @@ template <int R>
 __global__ void __launch_bounds__(kUT)
     k_upd_scatter(Hash h, const uint64_t *__restrict__ keys, uint64_t nkeys, uint32_t nsb,
                   uint32_t ntiles, const uint32_t *__restrict__ hist, uint64_t *ekey,
-                  uint16_t *eloc) {
+                  uint16_t *eloc, const unsigned long long *nkeys_dev) {
+  if (nkeys_dev) nkeys = *nkeys_dev;
   constexpr int kKPT = (int)(kUChunk / kUT) / R;      // keys per thread per chunk
   constexpr uint32_t kCK = (uint32_t)kKPT * kUT;      // keys per chunk
   static_assert(kKPT >= 1 && kCK * R <= kUChunk, "a chunk's entries fit in LDS");
@@ -365,6 +367,7 @@ struct ListCtrl {
   uint32_t qn[3];                // subtables mode: candidate queue of subround s has qn[s % 3]
   uint32_t pad2;
   unsigned long long nonempty;   // signed listing: cells left non-zero
+  unsigned long long first_keys; // binned first round: the keys it listed
   uint64_t stamp[256];           // wall clock at each barrier generation (diagnostic)
 };
 
@@ -389,6 +392,7 @@ struct ListArgs {
   uint32_t max_rounds;
   uint32_t cb;
   uint32_t grid;
+  uint32_t first_binned;  // round 1 ran before the launch: outputs and rounds follow it
 };
 
 __global__ void k_list_init(ListCtrl *ctrl) {
@@ -400,6 +404,55 @@ __global__ void k_list_init(ListCtrl *ctrl) {
 // twice in a round, since its count can pass +-1 twice); the listing clears it.
 __device__ inline bool claim_cell(iblt_cell *cells, uint32_t c) {
   return atomicCAS(&cells[c].reserved0, 0u, 1u) == 0u;
+}
+
+// Round 1 of a plain listing whose removals go through the binned update:
+// every pure cell that owns its key (the test of the persistent kernel's first
+// detect) gives its key to out.  Each workgroup scans a contiguous range of
+// cells and stages its keys in LDS; a full stage takes its place in out with
+// one device atomic on ctrl->first_keys.  The table is only read.
+constexpr uint32_t kD1Cap = 8192;  // keys staged per workgroup before they are written
+template <int R>
+__global__ void __launch_bounds__(kBlock)
+    k_list_detect1(Hash h, const iblt_cell *cells, uint32_t N, uint64_t *out, ListCtrl *ctrl) {
+  __shared__ uint64_t sk[kD1Cap];
+  __shared__ uint32_t s_n;
+  __shared__ unsigned long long s_base;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (N + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = (uint64_t)blockIdx.x * per;
+  const uint32_t c0 = lo < N ? static_cast<uint32_t>(lo) : N;
+  const uint32_t c1 = N - c0 < per ? N : c0 + per;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  auto flush = [&]() {  // every thread; s_n is final
+    const uint32_t n = s_n;
+    if (tid == 0) s_base = n ? atomicAdd(&ctrl->first_keys, (unsigned long long)n) : 0ull;
+    __syncthreads();
+    const unsigned long long base = s_base;
+    for (uint32_t i = tid; i < n; i += kBlock) out[base + i] = sk[i];
+    __syncthreads();
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+  };
+  uint32_t bad = 0;
+  for (uint32_t cb = c0; cb < c1; cb += kBlock) {
+    const uint32_t c = cb + tid;
+    bool own = false;
+    uint64_t ks = 0;
+    if (c < c1) {
+      int32_t cnt;
+      uint64_t hs;
+      load_cell(cells + c, &cnt, &ks, &hs);
+      own = owns<R, false>(h, cells, c, cnt, ks, hs, &bad);
+    }
+    const uint32_t pos = wave_append(own, &s_n);
+    if (own) sk[pos] = ks;
+    __syncthreads();
+    if (s_n + kBlock > kD1Cap) flush();  // the next step could overflow the stage
+  }
+  flush();
+  if (bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
 }
 
 template <int R, bool SIGNED = false>
@@ -418,6 +471,15 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
   uint64_t *myKeys = a.skeys + (uint64_t)slot * cb;
   uint32_t *myOwn = a.scells + (uint64_t)slot * cb;
   uint32_t *myCand = a.cand + (uint64_t)slot * cb;
+  // after a binned first round (launched before this kernel), this kernel's
+  // rounds are the run's rounds 2, 3, ... and their keys follow round 1's
+  uint64_t *out = a.out;
+  uint64_t out_cap = a.out_cap;
+  if (a.first_binned) {
+    const uint64_t f = ctrl->first_keys;
+    out += f;
+    out_cap = out_cap > f ? out_cap - f : 0;
+  }
 
   auto stage = [&](uint64_t x, uint32_t c, uint32_t parity) {
     const uint32_t pos = atomicAdd(&s_own, 1u);
@@ -474,7 +536,7 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
   for (;; ++t) {
     const uint64_t K = total + ovf;
     if (K == 0) break;
-    if (t > a.max_rounds || listed + K > a.out_cap) {
+    if (t > a.max_rounds || listed + K > out_cap) {
       if (slot == 0 && tid == 0)
         atomicOr(&ctrl->flags, t > a.max_rounds ? PEEL_FLAG_EROUNDS : PEEL_FLAG_ENOSPC);
       if (SIGNED) {  // give back the claims of the round that does not run
@@ -485,11 +547,11 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
     }
     // outputs of round t, grouped after the previous rounds
     for (uint32_t i = tid; i < staged; i += kLT) {
-      a.out[listed + prefix + i] = myKeys[i];
+      out[listed + prefix + i] = myKeys[i];
       if (SIGNED) a.signs[listed + prefix + i] = static_cast<int8_t>(a.cells[myOwn[i]].count);
     }
     for (uint64_t j = gtid; j < ovf; j += gsize) {
-      a.out[listed + total + j] = a.okeys[j];
+      out[listed + total + j] = a.okeys[j];
       if (SIGNED) a.signs[listed + total + j] = static_cast<int8_t>(a.cells[a.ocells[j]].count);
     }
     if (slot == 0 && tid == 0) {
@@ -790,15 +852,27 @@ __global__ void __launch_bounds__(kBlock) k_count_nonempty(const iblt_cell *cell
   if (threadIdx.x == 0 && tot) atomicAdd(&ctrl->nonempty, (unsigned long long)tot);
 }
 
+// first_binned: round 1 ran before the persistent kernel, which counted the
+// keys it left (count_sum) and its own rounds and keys; stats[0] gets round 1.
 __global__ void k_list_finish(const ListCtrl *ctrl, uint32_t r, uint64_t *summary,
-                              uint32_t signed_list) {
+                              uint32_t signed_list, uint64_t *stats, uint32_t first_binned) {
   if (threadIdx.x != 0) return;
   const long long total = (long long)ctrl->count_sum;
   const long long keys = total / (long long)r;
   uint32_t flags = ctrl->flags;
   if (ctrl->bar.abort) flags |= PEEL_FLAG_TIMEOUT;
-  summary[0] = ctrl->listed;
-  summary[1] = ctrl->rounds;
+  uint64_t listed = ctrl->listed;
+  uint32_t rounds = ctrl->rounds;
+  if (first_binned) {
+    const uint64_t f = ctrl->first_keys;
+    stats[0] = f;
+    if (f) {
+      listed += f;
+      rounds += 1;
+    }
+  }
+  summary[0] = listed;
+  summary[1] = rounds;
   summary[2] = signed_list ? (uint64_t)ctrl->nonempty : (uint64_t)(keys - (long long)ctrl->listed);
   summary[3] = flags;
   summary[4] = ctrl->team_size;
@@ -1220,10 +1294,12 @@ size_t upd_ws_bytes(const iblt_desc *d, uint64_t nkeys) {
          align_up(z.entries * 8) + align_up(z.entries * 2);
 }
 
+// nkeys_dev (if given): the key count, read on the device; nkeys is then the
+// most there can be and sizes the grids and the workspace.
 template <int R>
 peel_status launch_update_binned(const Hash &h, const iblt_desc *d, iblt_cell *cells,
                                  const uint64_t *keys, uint64_t nkeys, int32_t sign, void *ws,
-                                 hipStream_t s) {
+                                 hipStream_t s, const unsigned long long *nkeys_dev = nullptr) {
   const UpdSizes z = upd_sizes(d, nkeys);
   Carver c(ws);
   uint32_t *hist = c.take<uint32_t>(z.hist);
@@ -1232,10 +1308,10 @@ peel_status launch_update_binned(const Hash &h, const iblt_desc *d, iblt_cell *c
   uint64_t *ekey = c.take<uint64_t>(z.entries);
   uint16_t *eloc = c.take<uint16_t>(z.entries);
   hipLaunchKernelGGL(k_upd_count<R>, dim3(z.ntiles), dim3(kUT), 0, s, h, keys, nkeys, z.nsb,
-                     z.ntiles, hist);
+                     z.ntiles, hist, nkeys_dev);
   scan_u32(hist, z.hist, hist, nullptr, part, nullptr, total, nullptr, s);
   hipLaunchKernelGGL(k_upd_scatter<R>, dim3(z.ntiles), dim3(kUT), 0, s, h, keys, nkeys, z.nsb,
-                     z.ntiles, hist, ekey, eloc);
+                     z.ntiles, hist, ekey, eloc, nkeys_dev);
   hipLaunchKernelGGL(k_upd_apply<R>, dim3(z.nsb * kUPer), dim3(kUT), 0, s, h, cells, d->ncells,
                      ekey, eloc, hist, z.nsb, z.ntiles, total, sign);
   PEEL_HIP_TRY(hipGetLastError());
@@ -1289,8 +1365,43 @@ extern "C" peel_status iblt_delete(const iblt_desc *desc, iblt_cell *cells, cons
   return update_run(desc, cells, keys, nkeys, stream, -1);
 }
 
+namespace peel {
+namespace {
+
+// A plain listing of a large table on the whole GPU runs its first round's
+// removals through the binned update (its keys are the first round's output).
+constexpr uint64_t kListBinnedMin = 1ull << 20;
+
+bool list_first_binned_fits(const iblt_desc *d) {
+  return d->workgroups == 0 && d->ncells >= kListBinnedMin && upd_binned(d, d->ncells);
+}
+
+size_t list_ws_bytes(const iblt_desc *d) {
+  const ListLayout L = list_layout(d->ncells, d->workgroups);
+  size_t need = L.total;
+  if (list_first_binned_fits(d)) {
+    const size_t b = L.ctrl + upd_ws_bytes(d, d->ncells);
+    need = b > need ? b : need;
+  }
+  return need;
+}
+
+template <int R>
+peel_status first_round_binned(const iblt_desc *d, const Hash &h, iblt_cell *cells, uint64_t *out,
+                                ListCtrl *ctrl, void *ws, hipStream_t s) {
+  const uint32_t N = static_cast<uint32_t>(d->ncells);
+  const uint32_t grid = static_cast<uint32_t>(4 * device_info().cus);
+  hipLaunchKernelGGL(k_list_detect1<R>, dim3(grid), dim3(kBlock), 0, s, h, cells, N, out, ctrl);
+  PEEL_HIP_TRY(hipGetLastError());
+  // every key of round 1 leaves its r cells; its own cell comes out empty
+  return launch_update_binned<R>(h, d, cells, out, d->ncells, -1, ws, s, &ctrl->first_keys);
+}
+
+}  // namespace
+}  // namespace peel
+
 extern "C" size_t iblt_list_workspace(const iblt_desc *desc) {
-  return desc_ok(desc) ? list_layout(desc->ncells, desc->workgroups).total : 0;
+  return desc_ok(desc) ? list_ws_bytes(desc) : 0;
 }
 
 namespace peel {
@@ -1308,7 +1419,7 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
   if (ws_bytes < L.total) return PEEL_ENOSPC;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char *base = static_cast<char *>(ws);
-  ListArgs a;
+  ListArgs a{};
   a.h = make_hash(*desc);
   a.ctrl = reinterpret_cast<ListCtrl *>(base);
   base += L.ctrl;
@@ -1335,9 +1446,30 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
   a.max_rounds = max_rounds;
   a.cb = L.cb;
   a.grid = L.grid;
+  a.first_binned = 0;
   hipLaunchKernelGGL(k_list_init, dim3(1), dim3(256), 0, s, a.ctrl);
   PEEL_HIP_TRY(hipGetLastError());
   peel_status st;
+  // Round 1 binned: a plain listing with room for every key (so round 1 always
+  // runs, as in the persistent kernel) and at least two rounds allowed; the
+  // persistent kernel then runs rounds 2, 3, ... with one round fewer allowed.
+  if (!subtables && !signed_list && out_cap >= desc->ncells && max_rounds >= 2 &&
+      list_first_binned_fits(desc) && ws_bytes >= list_ws_bytes(desc)) {
+    void *bws = static_cast<char *>(ws) + L.ctrl;
+    switch (desc->r) {
+      case 2: st = first_round_binned<2>(desc, a.h, cells, out_keys, a.ctrl, bws, s); break;
+      case 3: st = first_round_binned<3>(desc, a.h, cells, out_keys, a.ctrl, bws, s); break;
+      case 4: st = first_round_binned<4>(desc, a.h, cells, out_keys, a.ctrl, bws, s); break;
+      case 5: st = first_round_binned<5>(desc, a.h, cells, out_keys, a.ctrl, bws, s); break;
+      case 6: st = first_round_binned<6>(desc, a.h, cells, out_keys, a.ctrl, bws, s); break;
+      case 7: st = first_round_binned<7>(desc, a.h, cells, out_keys, a.ctrl, bws, s); break;
+      default: st = first_round_binned<8>(desc, a.h, cells, out_keys, a.ctrl, bws, s); break;
+    }
+    if (st) return st;
+    a.first_binned = 1;
+    a.stats = round_stats + 1;
+    a.max_rounds = max_rounds - 1;
+  }
   switch (desc->r) {
     case 2: st = launch_list<2>(a, s, subtables); break;
     case 3: st = launch_list<3>(a, s, subtables); break;
@@ -1352,7 +1484,7 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
     hipLaunchKernelGGL(k_count_nonempty, dim3(grid_for(desc->ncells, kBlock * 8, 4096)),
                        dim3(kBlock), 0, s, cells, desc->ncells, a.ctrl);
   hipLaunchKernelGGL(k_list_finish, dim3(1), dim3(64), 0, s, a.ctrl, desc->r, summary,
-                     signed_list ? 1u : 0u);
+                     signed_list ? 1u : 0u, round_stats, a.first_binned);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }
