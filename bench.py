@@ -417,6 +417,8 @@ def main():
     ap.add_argument("--no-subtables", action="store_true",
                     help="skip the subtables peel (profiles of the main workload alone)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--iblt-main", action="store_true",
+                    help="of the IBLT workloads, only the 2^24-cell main one (profiles of one shape)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=5000, help="measured requests per rate")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy")
@@ -467,9 +469,10 @@ def main():
         extra["batched_partial"] = bench_batched(configs.batched_partial(), 3)
     if not args.no_iblt:
         log("IBLT 2^24 cells")
-        extra["iblt"] = [bench_iblt(configs.iblt_main(), 5),
-                         bench_iblt(configs.iblt_paper(3, 0.75), 5)]
-        extra["iblt_signed"] = bench_signed(5)
+        extra["iblt"] = [bench_iblt(configs.iblt_main(), 5)]
+        if not args.iblt_main:
+            extra["iblt"].append(bench_iblt(configs.iblt_paper(3, 0.75), 5))
+            extra["iblt_signed"] = bench_signed(5)
     torch.cuda.empty_cache()
     if not args.no_serve:
         log("served decoding")
