@@ -66,6 +66,17 @@ def test_update_deletes_and_reserved_words():
     _run(ncells, r, 77, a, dels=b, reserved=True)
     say("update with no keys")
     _run(4096, 3, 5, np.zeros(0, np.uint64))
+    # repeated keys (outside the insert precondition): the binned update still
+    # leaves the cells exactly as the per-key atomics do
+    say("update with repeated keys")
+    dup = np.concatenate([pool[:50000], pool[:20000], pool[10000:15000]])
+    d = pk.iblt_desc(ncells, r, 78)
+    x = pk.iblt_table(ncells, "cuda")
+    y = pk.iblt_table(ncells, "cuda")
+    pk.iblt_update(d, x, dev_u64(dup), 1)
+    pk.iblt_insert(d, y, dev_u64(dup))
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
 
 
 def test_update_full_size():
