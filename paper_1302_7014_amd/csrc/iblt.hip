@@ -318,6 +318,40 @@ __device__ inline bool owns(const Hash &h, const iblt_cell *cells, uint32_t c, i
   return true;
 }
 
+// Runs the owner test on cells cell_at(i) for i = i0 + tid, i0 + tid + nt, ...
+// below i1.  kDetU cells per lane are loaded before any is tested, so a lane has
+// kDetU loads in flight instead of one: the scan of a table in HBM is bound by
+// load latency, not bandwidth, with one.  take(key, cell) gets every owned key;
+// *sum gets the counts of the cells read.
+constexpr int kDetU = 4;
+template <int R, bool SIGNED, typename At, typename Take>
+__device__ inline void detect_cells(const Hash &h, const iblt_cell *cells, uint64_t i0, uint64_t i1,
+                                    uint32_t tid, uint32_t nt, At cell_at, Take take,
+                                    uint32_t *bad, long long *sum) {
+  for (uint64_t ib = i0 + tid; ib < i1; ib += (uint64_t)kDetU * nt) {
+    uint32_t c[kDetU];
+    int32_t cnt[kDetU];
+    uint64_t ks[kDetU], hs[kDetU];
+#pragma unroll
+    for (int u = 0; u < kDetU; ++u) {
+      const uint64_t i = ib + (uint64_t)u * nt;
+      c[u] = 0;
+      cnt[u] = 0;
+      ks[u] = hs[u] = 0;
+      if (i < i1) {
+        c[u] = cell_at(i);
+        load_cell(cells + c[u], &cnt[u], &ks[u], &hs[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kDetU; ++u) {
+      *sum += cnt[u];  // 0 for the places past i1
+      if (ib + (uint64_t)u * nt < i1 && owns<R, SIGNED>(h, cells, c[u], cnt[u], ks[u], hs[u], bad))
+        take(ks[u], c[u]);
+    }
+  }
+}
+
 // Deletes key x from its R cells; the cell it was listed from (c_own) is simply
 // cleared.  Calls push(c) for every cell whose count goes 2 -> 1.
 // SIGNED: x leaves with its sign (count -= sign) and a cell whose count lands on
@@ -411,7 +445,7 @@ __device__ inline bool claim_cell(iblt_cell *cells, uint32_t c) {
 // detect) gives its key to out.  Each workgroup scans a contiguous range of
 // cells and stages its keys in LDS; a full stage takes its place in out with
 // one device atomic on ctrl->first_keys.  The table is only read.
-constexpr uint32_t kD1Cap = 8192;  // keys staged per workgroup before they are written
+constexpr uint32_t kD1Cap = 4096;  // keys staged per workgroup before they are written
 template <int R>
 __global__ void __launch_bounds__(kBlock)
     k_list_detect1(Hash h, const iblt_cell *cells, uint32_t N, uint64_t *out, ListCtrl *ctrl) {
@@ -436,20 +470,15 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
   };
   uint32_t bad = 0;
-  for (uint32_t cb = c0; cb < c1; cb += kBlock) {
-    const uint32_t c = cb + tid;
-    bool own = false;
-    uint64_t ks = 0;
-    if (c < c1) {
-      int32_t cnt;
-      uint64_t hs;
-      load_cell(cells + c, &cnt, &ks, &hs);
-      own = owns<R, false>(h, cells, c, cnt, ks, hs, &bad);
-    }
-    const uint32_t pos = wave_append(own, &s_n);
-    if (own) sk[pos] = ks;
+  long long unused = 0;
+  constexpr uint32_t kStep = kDetU * kBlock;  // cells per step, kDetU per lane
+  for (uint64_t cb = c0; cb < c1; cb += kStep) {
+    const uint64_t ce = c1 - cb < kStep ? c1 : cb + kStep;
+    detect_cells<R, false>(
+        h, cells, cb, ce, tid, kBlock, [](uint64_t i) { return static_cast<uint32_t>(i); },
+        [&](uint64_t ks, uint32_t) { sk[wave_append(true, &s_n)] = ks; }, &bad, &unused);
     __syncthreads();
-    if (s_n + kBlock > kD1Cap) flush();  // the next step could overflow the stage
+    if (s_n + kStep > kD1Cap) flush();  // the next step could overflow the stage
   }
   flush();
   if (bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
@@ -508,14 +537,12 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
     const uint32_t c1 = c0 + cr < N ? c0 + cr : N;
     long long local = 0;
     uint32_t bad = 0;
-    for (uint32_t c = c0 + tid; c < c1; c += kLT) {
-      int32_t cnt;
-      uint64_t ks, hs;
-      load_cell(a.cells + c, &cnt, &ks, &hs);
-      local += cnt;
-      if (owns<R, SIGNED>(a.h, a.cells, c, cnt, ks, hs, &bad) && (!SIGNED || claim_cell(a.cells, c)))
-        stage(ks, c, 1u);
-    }
+    detect_cells<R, SIGNED>(
+        a.h, a.cells, c0, c1, tid, kLT, [](uint64_t i) { return static_cast<uint32_t>(i); },
+        [&](uint64_t ks, uint32_t c) {
+          if (!SIGNED || claim_cell(a.cells, c)) stage(ks, c, 1u);
+        },
+        &bad, &local);
     if (bad) s_bad = 1;
     atomicAdd(&s_sum, (unsigned long long)local);
   }
@@ -590,24 +617,19 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
     __syncthreads();
     {
       uint32_t bad = 0;
-      for (uint32_t i = tid; i < ncand; i += kLT) {
-        const uint32_t c = myCand[i];
-        int32_t cnt;
-        uint64_t ks, hs;
-        load_cell(a.cells + c, &cnt, &ks, &hs);
-        if (owns<R, SIGNED>(a.h, a.cells, c, cnt, ks, hs, &bad) && (!SIGNED || claim_cell(a.cells, c)))
-          stage(ks, c, npar);
-      }
+      long long unused = 0;
+      auto take = [&](uint64_t ks, uint32_t c) {
+        if (!SIGNED || claim_cell(a.cells, c)) stage(ks, c, npar);
+      };
+      detect_cells<R, SIGNED>(
+          a.h, a.cells, 0, ncand, tid, kLT, [&](uint64_t i) { return myCand[i]; }, take, &bad,
+          &unused);
       const uint32_t ovc =
           __hip_atomic_load(&ctrl->ovf_cand[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      for (uint64_t j = gtid; j < ovc; j += gsize) {
-        const uint32_t c = a.ocand[(uint64_t)par * N + j];
-        int32_t cnt;
-        uint64_t ks, hs;
-        load_cell(a.cells + c, &cnt, &ks, &hs);
-        if (owns<R, SIGNED>(a.h, a.cells, c, cnt, ks, hs, &bad) && (!SIGNED || claim_cell(a.cells, c)))
-          stage(ks, c, npar);
-      }
+      const uint32_t *oc = a.ocand + (uint64_t)par * N;
+      detect_cells<R, SIGNED>(
+          a.h, a.cells, (uint64_t)slot * kLT, ovc, tid, (uint32_t)gsize,
+          [&](uint64_t i) { return oc[i]; }, take, &bad, &unused);
       if (bad) s_bad = 1;
     }
     __syncthreads();
