@@ -397,23 +397,33 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
       __syncthreads();
       uint32_t nc = 0;  // claims so far (same in every thread)
-      for (uint32_t c0 = 0; c0 < fcnt; c0 += kOT) {
-        uint32_t st = 0, len = 0;
-        if (c0 + tid < fcnt) {
-          const uint32_t v = myF[c0 + tid];
+      // frontier vertex i leaves; its list's start and length (0 for a vertex
+      // of degree 0, which holds no alive edge)
+      auto take_list = [&](uint32_t i, uint32_t &st, uint32_t &len) {
+        st = 0;
+        len = 0;
+        if (i < fcnt) {
+          const uint32_t v = myF[i];
           const uint32_t lv = v - v0;
           const uint32_t d4 = (deg4[lv >> 3] >> (4 * (lv & 7))) & kNib;
           mark_removed(v, lv, t);
-          if (d4 != 0) {  // a vertex of degree 0 holds no alive edge
+          if (d4 != 0) {
             st = a.offsets[v];
             len = a.offsets[v + 1] - st;
           }
         }
+      };
+      uint32_t st, len;
+      take_list(tid, st, len);
+      for (uint32_t c0 = 0; c0 < fcnt; c0 += kOT) {
         uint32_t tot;
         const uint32_t ex = block_exclusive_scan<kOT>(len, &tot, scan_lds);
         s_start[tid] = st;
         s_pre[tid] = ex;
         __syncthreads();
+        // the next chunk's offsets are loaded now, so that their latency
+        // overlaps that of this chunk's incidence loads
+        take_list(c0 + kOT + tid, st, len);
         for (uint32_t j0 = tid; j0 < tot; j0 += kLU * kOT) {
           uint32_t e[kLU];
 #pragma unroll
