@@ -154,6 +154,8 @@ def bench_kcore(spec, steps, warmup, subtables=False):
         "wall_s": wall, "m_removed": m_rem, "rounds": int(summ[0]), "edge_rounds": int(summ[1]),
         "core_vertices": int(summ[3]),
         "build_ms": float(np.mean(tb.ms)), "peel_ms": float(np.mean(tp.ms)),
+        "build_ms_p10_p90": [float(np.percentile(tb.ms, 10)), float(np.percentile(tb.ms, 90))],
+        "peel_ms_p10_p90": [float(np.percentile(tp.ms, 10)), float(np.percentile(tp.ms, 90))],
         "peel_bytes": peel_bytes(n, r, e_host, deg0, vr, er),
         "build_bytes": build_bytes(n, m, r), "edges_host": e_host,
     }
@@ -323,6 +325,9 @@ def bench_batched(spec, reps):
         "schedule": sched, "tuner_trials": trials,
         "batched_graph_ms": bt, "plain_per_table_ms": pt, "speedup": pt / bt,
         "batched_keys_per_s": listed / (bt * 1e-3), "plain_keys_per_s": listed_plain / (pt * 1e-3),
+        # the listing's algorithmic bytes summed over the tables (each table's
+        # 4N + listed (28 + 40r) adds up to the same form over the whole batch)
+        "batched_gbs": iblt_list_bytes(int(sum(x[0] for x in draw)), spec.r, listed) / (bt * 1e-3) / 1e9,
         "listed_equal": listed == listed_plain,
     }
 
@@ -373,6 +378,37 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}))
 
 
+def stream_copy_gbs(reps=5):
+    """Bandwidth of a plain 1 GiB device-to-device copy (read + write bytes per
+    second, median of `reps`): the practical HBM ceiling beside the 8 TB/s peak."""
+    dev = torch.device("cuda", 0)
+    a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    t = Timer()
+    for _ in range(reps):
+        with t:
+            b.copy_(a)
+    t.collect()
+    ms = float(np.median(t.ms))
+    del a, b
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "usable": len(os.sched_getaffinity(0))}
+
+
 def traffic_from_profile(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when the kernel's source changed since the counters were taken."""
@@ -403,7 +439,7 @@ def cpu_baseline(spec, e_host):
     m_rem = int((o.edge_round != 0).sum())
     return {"value": m_rem / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"one full run of oracle peel_rounds (its own CSR build included) on "
-                      f"{spec.name} ({spec.m} edges), {dt:.2f} s"}
+                      f"{spec.name} ({spec.m} edges), {dt:.2f} s", "host": host_cpu()}
 
 
 def main():
@@ -454,7 +490,13 @@ def main():
         "build_gbs": kc["build_bytes"] / (kc["build_ms"] * 1e-3) / 1e9,
         "rounds": kc["rounds"], "edge_rounds": kc["edge_rounds"],
         "core_vertices": kc["core_vertices"],
+        "peel_ms_p10_p90": kc["peel_ms_p10_p90"], "build_ms_p10_p90": kc["build_ms_p10_p90"],
     }
+    # the peel's algorithmic rate against what a plain device copy reaches
+    copy_gbs = stream_copy_gbs()
+    extra["stream_copy_gbs"] = copy_gbs
+    extra["peel_frac_of_copy"] = extra["peel_gbs"] / copy_gbs
+    extra["build_frac_of_copy"] = extra["build_gbs"] / copy_gbs
     if not args.no_subtables:
         # the paper's own schedule (peeling with subtables) on the same workload
         sb = bench_kcore(spec, max(3, args.steps // 2), 1, subtables=True)
