@@ -437,9 +437,17 @@ def cpu_baseline(spec, e_host):
     o = native.peel_rounds(spec.n, e_host, spec.k)
     dt = time.perf_counter() - t0
     m_rem = int((o.edge_round != 0).sum())
+    # the oracle's sequential queue peel (the serial process of Section 1), beside it
+    t0 = time.perf_counter()
+    _, core_e = native.peel_queue(spec.n, e_host, spec.k)
+    dq = time.perf_counter() - t0
+    mq = int(spec.m - core_e.sum())
     return {"value": m_rem / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"one full run of oracle peel_rounds (its own CSR build included) on "
-                      f"{spec.name} ({spec.m} edges), {dt:.2f} s", "host": host_cpu()}
+                      f"{spec.name} ({spec.m} edges), {dt:.2f} s", "host": host_cpu(),
+            "serial_queue": {"value": mq / dq, "unit": "edges/s", "cores": 1,
+                             "sample": f"one full run of oracle peel_queue on the same "
+                                       f"workload, {dq:.2f} s"}}
 
 
 def main():

@@ -52,3 +52,13 @@ def test_host_description():
     h = bench.host_cpu()
     assert isinstance(h["model"], str)
     assert h["nproc"] >= 1 and 1 <= h["usable"] <= h["nproc"]
+
+
+def test_cpu_baseline_on_the_small_workload():
+    from workloads import configs
+    spec = configs.kcore_small()
+    cb = bench.cpu_baseline(spec, spec.edges(1))
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0
+    # c = 0.70 < c*: both the round-synchronous and the serial peel remove every edge
+    assert cb["serial_queue"]["value"] > 0
+    assert str(spec.m) in cb["sample"]
