@@ -264,7 +264,11 @@ peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_key
  * Other arguments and limits as for iblt_list, except: a count of +-1 with a
  * wrong checksum is an ordinary cell here (never PEEL_FLAG_ECORRUPT), and
  * summary[2] is the number of cells left non-zero (0 means the difference
- * was listed whole).
+ * was listed whole).  A cell's count can land on +-1 more than once in a
+ * round, and each time the cell is queued for the next round's detect; if a
+ * round queues more cells than the workspace's queues hold (more than about
+ * 2 * ncells in all, far above what a table below the threshold does), the
+ * cells past that are not examined and PEEL_FLAG_ENOSPC is set.
  */
 peel_status iblt_list_signed(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,
                              int8_t *out_signs, uint64_t out_cap, uint64_t *round_stats,

@@ -589,12 +589,21 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
     if (tid == 0) s_cand = 0;
     __syncthreads();
     const uint32_t par = t & 1;
+    // A plain listing pushes a cell at most once a round (its count passes
+    // 2 -> 1 once), so the N overflow places always suffice.  A signed listing
+    // can push a cell again each time its count lands on +-1: past N places
+    // the cell is dropped and the call reports PEEL_FLAG_ENOSPC.
     auto push = [&](uint32_t c) {
       const uint32_t pos = atomicAdd(&s_cand, 1u);
-      if (pos < cb)
+      if (pos < cb) {
         myCand[pos] = c;
-      else
-        a.ocand[(uint64_t)par * N + atomicAdd(&ctrl->ovf_cand[par], 1u)] = c;
+      } else {
+        const uint32_t j = atomicAdd(&ctrl->ovf_cand[par], 1u);
+        if (j < N)
+          a.ocand[(uint64_t)par * N + j] = c;
+        else
+          atomicOr(&ctrl->flags, PEEL_FLAG_ENOSPC);
+      }
     };
     for (uint32_t i = tid; i < staged; i += kLT)
       delete_key<R, SIGNED>(a.h, a.cells, myKeys[i], myOwn[i], push,
@@ -624,8 +633,9 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
       detect_cells<R, SIGNED>(
           a.h, a.cells, 0, ncand, tid, kLT, [&](uint64_t i) { return myCand[i]; }, take, &bad,
           &unused);
-      const uint32_t ovc =
+      uint32_t ovc =
           __hip_atomic_load(&ctrl->ovf_cand[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ovc = ovc < N ? ovc : N;  // the places written (see push)
       const uint32_t *oc = a.ocand + (uint64_t)par * N;
       detect_cells<R, SIGNED>(
           a.h, a.cells, (uint64_t)slot * kLT, ovc, tid, (uint32_t)gsize,
@@ -1467,6 +1477,10 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
   a.ncells = static_cast<uint32_t>(desc->ncells);
   a.max_rounds = max_rounds;
   a.cb = L.cb;
+  // PEEL_LIST_SLOT_CAP: a smaller staging slot per workgroup, so that the
+  // overflow queues take the keys and candidates past it (for testing them)
+  const long slot_cap = env_long("PEEL_LIST_SLOT_CAP", 0);
+  if (slot_cap > 0 && (uint64_t)slot_cap < a.cb) a.cb = static_cast<uint32_t>(slot_cap);
   a.grid = L.grid;
   a.first_binned = 0;
   hipLaunchKernelGGL(k_list_init, dim3(1), dim3(256), 0, s, a.ctrl);

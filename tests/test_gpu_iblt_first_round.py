@@ -78,3 +78,20 @@ def test_large_table_limits_corrupt_and_old_paths():
     _check(N, 3, 5, gen.distinct_keys(300000, 40), corrupt=True)
     say("first round binned, empty table")
     _check(N, 3, 5, np.zeros(0, np.uint64))
+
+
+@pytest.mark.parametrize("ncells,r,frac,workgroups", [
+    ((1 << 18) + 5, 3, 0.8, 0),    # round 1 in the persistent kernel
+    ((1 << 18) + 5, 4, 1.2, 0),    # above threshold: a core is left
+    ((1 << 16) + 3, 3, 0.8, 7),    # a share of the CUs
+    (N, 3, 0.8, 0),                # binned first round, then the queues
+])
+def test_overflow_queues(monkeypatch, ncells, r, frac, workgroups):
+    # staging slots of 64 per workgroup: nearly every key and candidate goes
+    # through the shared overflow queues
+    need_gpu()
+    monkeypatch.setenv("PEEL_LIST_SLOT_CAP", "64")
+    m = int(frac * theory.cstar(2, r)[0] * ncells)
+    keys = gen.distinct_keys(m, 910 + r)
+    say("overflow queues", ncells, r, m, workgroups)
+    _check(ncells, r, gen.table_seed(910 + r), keys, workgroups=workgroups)

@@ -103,3 +103,18 @@ def test_signed_full_size_difference():
     say("signed full size", a.size, b.size)
     s, o = _run(N, 3, a, b, gen.table_seed(901))
     assert o.status == native.OK and int(s[2]) == 0
+
+
+@pytest.mark.parametrize("load", [0.5, 1.3])
+def test_signed_overflow_queues(monkeypatch, load):
+    # staging slots of 64 per workgroup: the overflow queues carry nearly all
+    # keys and candidates, and a cell queued twice in a round is listed once
+    need_gpu()
+    monkeypatch.setenv("PEEL_LIST_SLOT_CAP", "64")
+    N, r = (1 << 16) + 33, 3
+    d = load * theory.cstar(2, r)[0]
+    a, b = _sets(N, 0.6 * d + 0.2, 0.4 * d + 0.2, 0.4, 930)
+    say("signed overflow queues", load, a.size, b.size)
+    s, o = _run(N, r, a, b, gen.table_seed(930))
+    if load < 1:
+        assert o.status == native.OK and int(s[2]) == 0
