@@ -459,7 +459,8 @@ def main():
     ap.add_argument("--no-iblt", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="also time every c of the n=2^24 sweep")
     ap.add_argument("--no-subtables", action="store_true",
-                    help="skip the subtables peel (profiles of the main workload alone)")
+                    help="skip the subtables peel and the k = 3 peels (profiles of the main "
+                         "workload alone)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--iblt-main", action="store_true",
                     help="of the IBLT workloads, only the 2^24-cell main one (profiles of one shape)")
@@ -512,6 +513,18 @@ def main():
             "peel_ms": sb["peel_ms"], "subrounds": sb["rounds"], "edge_subrounds": sb["edge_rounds"],
             "peel_edges_per_s": sb["m_removed"] / (sb["peel_ms"] * 1e-3),
             "vs_rounds_peel_ms": kc["peel_ms"]}
+    if not args.no_subtables:
+        # k = 3 on r = 3, n = 2^22, below and above its threshold
+        k3 = []
+        for which in ("lo", "hi"):
+            s3 = configs.kcore_k3(which)
+            r3 = bench_kcore(s3, max(3, args.steps // 4), 1)
+            k3.append({"workload": s3.name, "m": s3.m, "rounds": r3["rounds"],
+                       "m_removed": r3["m_removed"], "core_vertices": r3["core_vertices"],
+                       "peel_ms": r3["peel_ms"], "build_ms": r3["build_ms"],
+                       "peel_edges_per_s": r3["m_removed"] / (r3["peel_ms"] * 1e-3),
+                       "peel_gbs": r3["peel_bytes"] / (r3["peel_ms"] * 1e-3) / 1e9})
+        extra["k3"] = k3
     if not args.no_batched:
         log("batched IBLT listing (4096 tables)")
         extra["batched"] = bench_batched(configs.batched_main(), 3)
