@@ -208,7 +208,8 @@ def bench_iblt(spec, reps):
     upd = float(np.median(tu.ms[2:]))
     return {
         "workload": spec.name, "cells": spec.ncells, "keys": spec.nkeys, "r": spec.r,
-        "listed": listed, "rounds": int(s[1]), "left": int(s[2]), "flags": int(s[3]),
+        "listed": listed, "recovered_frac": listed / spec.nkeys, "rounds": int(s[1]),
+        "left": int(s[2]), "flags": int(s[3]),
         "insert_ms": ins, "list_ms": lst, "insert_incl_h2d_ms": h2d,
         "insert_binned_ms": upd, "insert_binned_keys_per_s": spec.nkeys / (upd * 1e-3),
         "insert_keys_per_s": spec.nkeys / (ins * 1e-3),
@@ -534,7 +535,9 @@ def main():
         log("IBLT 2^24 cells")
         extra["iblt"] = [bench_iblt(configs.iblt_main(), 5)]
         if not args.iblt_main:
-            extra["iblt"].append(bench_iblt(configs.iblt_paper(3, 0.75), 5))
+            # the shapes of the paper's Tables 5 and 6: r = 3, 4 at loads 0.75, 0.83
+            for r_, load in ((3, 0.75), (3, 0.83), (4, 0.75), (4, 0.83)):
+                extra["iblt"].append(bench_iblt(configs.iblt_paper(r_, load), 5))
             extra["iblt_signed"] = bench_signed(5)
     torch.cuda.empty_cache()
     if not args.no_serve:
