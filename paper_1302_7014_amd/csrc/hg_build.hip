@@ -44,6 +44,7 @@ constexpr uint32_t kStageCap = 28672;           // incidences of a bucket staged
 constexpr uint64_t kTileEdges = 16384;          // edges per bin tile
 constexpr int kBT = 1024;                       // threads per workgroup in the bin kernels
 constexpr int kRowsU = 4;                       // edge rows per thread in flight in the count
+constexpr int kCT = 512;                        // threads per count workgroup: every tile resident at once
 constexpr uint32_t kSortPairs = 8192;           // pairs sorted in LDS per scatter chunk
 constexpr int kPairsU = 4;                      // pairs per thread in flight in the bucket build
 constexpr uint32_t kNone = ~0u;
@@ -56,15 +57,6 @@ inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 __device__ inline uint64_t ceil_div_dev(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline bool binned(uint32_t n) { return ceil_div(n, 1u << kSupShift) <= kMaxSuper; }
 
-// *out = maximum of in[0..count) (one workgroup).
-__global__ void __launch_bounds__(kBlock) k_max_u32(const uint32_t *in, uint64_t count, uint32_t *out) {
-  __shared__ uint32_t lds[kBlock / kWave + 1];
-  uint32_t mx = 0;
-  for (uint64_t i = threadIdx.x; i < count; i += kBlock) mx = in[i] > mx ? in[i] : mx;
-  mx = block_max(mx, lds);
-  if (threadIdx.x == 0) *out = mx;
-}
-
 // ---------------------------------------------------------------------------
 // Binned build.
 
@@ -75,27 +67,27 @@ __device__ inline uint32_t pad(uint32_t i) { return i + (i >> 5); }
 // hist8[b * ntiles + tile] = incidences of this edge tile whose vertex is in bucket b;
 // hist[s * ntiles + tile] = the same per super-bucket s.
 template <int R>
-__global__ void __launch_bounds__(kBT)
+__global__ void __launch_bounds__(kCT)
     k_bin_count(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t nb,
                 uint32_t nsb, uint64_t ntiles, uint32_t *hist, uint32_t *hist8, uint32_t *info) {
   __shared__ uint32_t h[kMaxSuper * kSubPer];
-  for (uint32_t b = threadIdx.x; b < nsb * kSubPer; b += kBT) h[b] = 0;
+  for (uint32_t b = threadIdx.x; b < nsb * kSubPer; b += kCT) h[b] = 0;
   __syncthreads();
   const uint32_t tile = xcd_item(blockIdx.x, static_cast<uint32_t>(ntiles));
   const uint64_t e0 = (uint64_t)tile * kTileEdges;
   const uint64_t e1 = e0 + kTileEdges < m ? e0 + kTileEdges : m;
   bool bad = false;
-  for (uint64_t eb = e0 + threadIdx.x; eb < e1; eb += kRowsU * kBT) {
+  for (uint64_t eb = e0 + threadIdx.x; eb < e1; eb += kRowsU * kCT) {
     uint32_t ids[kRowsU][R];
 #pragma unroll
     for (int u = 0; u < kRowsU; ++u) {
-      const uint64_t e = eb + (uint64_t)u * kBT;
+      const uint64_t e = eb + (uint64_t)u * kCT;
 #pragma unroll
       for (int j = 0; j < R; ++j) ids[u][j] = e < e1 ? edges[e * R + j] : kNone;
     }
 #pragma unroll
     for (int u = 0; u < kRowsU; ++u) {
-      if (eb + (uint64_t)u * kBT >= e1) continue;
+      if (eb + (uint64_t)u * kCT >= e1) continue;
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const uint32_t v = ids[u][j];
@@ -108,8 +100,8 @@ __global__ void __launch_bounds__(kBT)
   }
   if (bad) atomicOr(&info[0], PEEL_FLAG_ERANGE);
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb; b += kBT) hist8[(uint64_t)b * ntiles + tile] = h[b];
-  for (uint32_t sb = threadIdx.x; sb < nsb; sb += kBT) {
+  for (uint32_t b = threadIdx.x; b < nb; b += kCT) hist8[(uint64_t)b * ntiles + tile] = h[b];
+  for (uint32_t sb = threadIdx.x; sb < nsb; sb += kCT) {
     uint32_t c = 0;
 #pragma unroll
     for (int q = 0; q < kSubPer; ++q) c += h[sb * kSubPer + q];
@@ -299,7 +291,7 @@ template <typename P>
 __global__ void __launch_bounds__(kBT)
     k_bin_build(const P *__restrict__ pairs, uint32_t n, uint32_t nb, uint64_t ntiles,
                 const uint32_t *__restrict__ hist8, const uint32_t *total, uint32_t *offsets,
-                uint32_t *inc, uint32_t *deg, uint32_t *pmax) {
+                uint32_t *inc, uint32_t *deg, uint32_t *maxdeg) {
   constexpr bool kP4 = sizeof(P) == 4;
   __shared__ uint32_t cnt[kBinV + kBinV / 32];
   __shared__ uint32_t stage[kStageCap];
@@ -416,7 +408,7 @@ __global__ void __launch_bounds__(kBT)
   }
   const uint32_t bmax = block_max<kBT>(mx, lds);
   if (threadIdx.x == 0) {
-    pmax[b] = bmax;
+    if (bmax) atomicMax(maxdeg, bmax);  // *maxdeg starts at 0
     if (b == nb - 1) offsets[n] = end;
   }
   __syncthreads();
@@ -515,26 +507,25 @@ peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t
   uint32_t *part8 = c.take<uint32_t>(scan_tiles(z.hist8) + 1);
   uint64_t *pairs = c.take<uint64_t>(z.pairs ? z.pairs : 1);
   uint64_t *pairs2 = c.take<uint64_t>(z.pairs ? z.pairs : 1);
-  uint32_t *pmax = c.take<uint32_t>(z.nb + 4);
-  uint32_t *total = pmax + z.nb;      // pairs, from the super-bucket scan
-  uint32_t *total8 = pmax + z.nb + 1; // the same, from the bucket scan
+  uint32_t *sums = c.take<uint32_t>(z.nb + 4);
+  uint32_t *total = sums + z.nb;      // pairs, from the super-bucket scan
+  uint32_t *total8 = sums + z.nb + 1; // the same, from the bucket scan
   const bool flat = z.ntiles && z.nb <= kMaxB4 && z.ntiles <= kMaxTiles4;
   if (flat) {
     // two levels: tiles to (bucket, tile) runs of 4-byte pairs, then buckets
-    hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
+    hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kCT), 0, s, edges, m, n,
                        (uint32_t)z.nb, (uint32_t)z.nsb, z.ntiles, hist, hist8, info);
     scan_u32(hist8, z.hist8, hist8, nullptr, part8, nullptr, total8, nullptr, s);
     uint32_t *pairs4 = reinterpret_cast<uint32_t *>(pairs);
     hipLaunchKernelGGL(k_bin_scatter4<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
                        (uint32_t)z.nb, z.ntiles, hist8, pairs4);
     hipLaunchKernelGGL(k_bin_build<uint32_t>, dim3(z.nb), dim3(kBT), 0, s, pairs4, n,
-                       (uint32_t)z.nb, z.ntiles, hist8, total8, offsets, inc, deg, pmax);
-    hipLaunchKernelGGL(k_max_u32, dim3(1), dim3(kBlock), 0, s, pmax, z.nb, info + 1);
+                       (uint32_t)z.nb, z.ntiles, hist8, total8, offsets, inc, deg, info + 1);
     PEEL_HIP_TRY(hipGetLastError());
     return PEEL_OK;
   }
   if (z.ntiles) {
-    hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
+    hipLaunchKernelGGL(k_bin_count<R>, dim3(z.ntiles), dim3(kCT), 0, s, edges, m, n,
                        (uint32_t)z.nb, (uint32_t)z.nsb, z.ntiles, hist, hist8, info);
     scan_u32(hist, z.hist, hist, nullptr, part, nullptr, total, nullptr, s);
     scan_u32(hist8, z.hist8, hist8, nullptr, part8, nullptr, total8, nullptr, s);
@@ -550,8 +541,7 @@ peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(kBlock), 0, s, total8, (uint64_t)1, 0u);
   }
   hipLaunchKernelGGL(k_bin_build<uint64_t>, dim3(z.nb), dim3(kBT), 0, s, pairs2, n, (uint32_t)z.nb,
-                     z.ntiles ? z.ntiles : 1, hist8, total8, offsets, inc, deg, pmax);
-  hipLaunchKernelGGL(k_max_u32, dim3(1), dim3(kBlock), 0, s, pmax, z.nb, info + 1);
+                     z.ntiles ? z.ntiles : 1, hist8, total8, offsets, inc, deg, info + 1);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
 }
