@@ -168,9 +168,9 @@ class _Base:
         q._table = pk.BatchTable(desc, cells, keys_out, stats, summ)
         return True
 
-    def _retire(self, q: Request, now: float) -> None:
+    def _retire(self, q: Request, now: float, summary: np.ndarray | None = None) -> None:
         q.done = now
-        q.summary = q._table.summary.cpu().numpy().copy()
+        q.summary = q._table.summary.cpu().numpy().copy() if summary is None else summary
         if self.keep_keys:
             listed = int(q.summary[0])
             q.keys_out = q._table.keys[:listed].cpu().numpy().view(np.uint64).copy()
@@ -273,8 +273,10 @@ class ContinuousServer(_Base):
             for ev, qs, slot, ent in inflight:
                 if ev.query():
                     tnow = time.perf_counter() - t0
-                    for q in qs:
-                        self._retire(q, tnow)
+                    # the batch's summaries in one copy rather than one per table
+                    sums = torch.stack([q._table.summary for q in qs]).cpu().numpy()
+                    for q, srow in zip(qs, sums):
+                        self._retire(q, tnow, srow.copy())
                         done.append(q)
                     free_slots.append(slot)
                 else:
