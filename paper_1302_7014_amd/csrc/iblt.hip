@@ -320,9 +320,9 @@ __device__ inline bool owns(const Hash &h, const iblt_cell *cells, uint32_t c, i
 
 // Runs the owner test on cells cell_at(i) for i = i0 + tid, i0 + tid + nt, ...
 // below i1.  kDetU cells per lane are loaded before any is tested, so a lane has
-// kDetU loads in flight instead of one: the scan of a table in HBM is bound by
-// load latency, not bandwidth, with one.  take(key, cell) gets every owned key;
-// *sum gets the counts of the cells read.
+// kDetU loads in flight: with one, a scan of a table in HBM is bound by load
+// latency rather than bandwidth.  take(key, cell) gets every owned key; *sum
+// gets the counts of the cells read.
 constexpr int kDetU = 4;
 template <int R, bool SIGNED, typename At, typename Take>
 __device__ inline void detect_cells(const Hash &h, const iblt_cell *cells, uint64_t i0, uint64_t i1,
