@@ -55,6 +55,8 @@ typedef int32_t peel_status;
 #define PEEL_FLAG_ECORRUPT 0x8u
 #define PEEL_FLAG_TIMEOUT 0x10u /* a device-wide barrier waited past its limit; */
                                 /* the call's other outputs are then undefined  */
+#define PEEL_FLAG_EINVAL 0x20u  /* a batch entry was rejected (r, size, or      */
+                                /* alignment); that table was left untouched    */
 
 /* Human-readable name of a status code; never NULL. */
 const char *peel_strerror(peel_status s);
@@ -318,7 +320,10 @@ peel_status iblt_list_subtables(const iblt_desc *desc, iblt_cell *cells, uint64_
  *                 256, 512 or 1024 (0 = 512) and lds_max_cells at most
  *                 IBLT_LDS_MAX_CELLS, else PEEL_EINVAL.
  *   ws            (device) ws_bytes >= iblt_list_batched_workspace().
- * Each table's summary is written as iblt_list's ([4] = 1 workgroup).
+ * Each table's summary is written as iblt_list's ([4] = 1 workgroup).  An
+ * entry with r outside 2..8, ncells < r, ncells > max_cells, or cells that are
+ * null or not 32-byte aligned is not listed: its summary (if not null) gets
+ * [3] = PEEL_FLAG_EINVAL and zeros elsewhere, and the other tables go on.
  */
 #define IBLT_LDS_MAX_CELLS 2048u
 

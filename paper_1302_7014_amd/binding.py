@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(HERE, "libpeel.so")
 
 PEEL_OK, PEEL_EINVAL, PEEL_ERANGE, PEEL_ENOSPC, PEEL_EROUNDS, PEEL_ECORRUPT, PEEL_EHIP = (
     0, -1, -2, -3, -4, -5, -6)
-FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT = 0x1, 0x2, 0x4, 0x8, 0x10
+FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT, FLAG_EINVAL = (
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
 
 # Every symbol include/peel.h declares.
 EXPORTS = ("peel_strerror", "peel_abi_version", "hg_build_workspace", "hg_build",
@@ -113,6 +114,17 @@ def workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def _call_ws(nbytes: int, device, stream) -> torch.Tensor:
+    """A workspace a wrapper allocates for one call.  The allocator hands it out
+    on the current stream; when the call runs on another stream the tensor is
+    marked as used there, so that its memory is not reused before that stream
+    has finished with it."""
+    ws = workspace(nbytes, device)
+    if stream is not None and stream != torch.cuda.current_stream(ws.device):
+        ws.record_stream(stream)
+    return ws
+
+
 # ---------------------------------------------------------------------------
 @dataclass
 class Csr:
@@ -135,7 +147,7 @@ def hg_build(edges: torch.Tensor, n: int, out: Csr | None = None, ws: torch.Tens
         out = Csr(_empty(n + 1, torch.int32, dev), _empty(m * r, torch.int32, dev),
                   _empty(n, torch.int32, dev), _empty(2, torch.int32, dev))
     if ws is None:
-        ws = workspace(hg_build_workspace(n, m, r), dev)
+        ws = _call_ws(hg_build_workspace(n, m, r), dev, stream)
     _check(lib().hg_build(_ptr(edges), m, r, n, _ptr(out.offsets), _ptr(out.inc), _ptr(out.deg),
                           _ptr(out.info), _ptr(ws), ws.numel(), _stream(stream)), "hg_build")
     return out
@@ -169,7 +181,7 @@ def peel_kcore(edges: torch.Tensor, n: int, k: int, csr: Csr, max_rounds: int = 
         out = PeelOut(csr.deg, _empty(n, torch.int32, dev), _empty(m, torch.int32, dev),
                       _empty(2 * max_rounds, torch.int64, dev), _empty(8, torch.int32, dev))
     if ws is None:
-        ws = workspace(peel_kcore_workspace(n, m, r), dev)
+        ws = _call_ws(peel_kcore_workspace(n, m, r), dev, stream)
     fn = lib().peel_kcore_subtables if subtables else lib().peel_kcore
     _check(fn(_ptr(edges), m, r, n, k, _ptr(csr.offsets), _ptr(csr.inc),
               _ptr(out.deg), _ptr(out.vertex_round), _ptr(out.edge_round),
@@ -209,7 +221,7 @@ def iblt_update(desc: IbltDesc, cells: torch.Tensor, keys: torch.Tensor, sign: i
     """iblt_insert (sign=+1) or iblt_delete (sign=-1) by binning the keys per
     block of cells: the same cells, without a device atomic per update."""
     if ws is None:
-        ws = workspace(iblt_update_workspace(desc, keys.numel()), cells.device)
+        ws = _call_ws(iblt_update_workspace(desc, keys.numel()), cells.device, stream)
     _check(lib().iblt_update(C.byref(desc), _ptr(cells), _ptr(keys), keys.numel(), sign, _ptr(ws),
                              ws.numel(), _stream(stream)), "iblt_update")
 
@@ -237,7 +249,7 @@ def iblt_list(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = None,
                       _empty(8, torch.int64, dev))
     cap = out.keys.numel() if out_cap is None else out_cap
     if ws is None:
-        ws = workspace(iblt_list_workspace(desc), dev)
+        ws = _call_ws(iblt_list_workspace(desc), dev, stream)
     fn = lib().iblt_list_subtables if subtables else lib().iblt_list
     _check(fn(C.byref(desc), _ptr(cells), _ptr(out.keys), cap, _ptr(out.round_stats),
               max_rounds, _ptr(out.summary), _ptr(ws), ws.numel(), _stream(stream)),
@@ -264,7 +276,7 @@ def iblt_list_signed(desc: IbltDesc, cells: torch.Tensor, out_cap: int | None = 
                             _empty(max_rounds, torch.int64, dev), _empty(8, torch.int64, dev))
     cap = out.keys.numel() if out_cap is None else out_cap
     if ws is None:
-        ws = workspace(iblt_list_workspace(desc), dev)
+        ws = _call_ws(iblt_list_workspace(desc), dev, stream)
     _check(lib().iblt_list_signed(C.byref(desc), _ptr(cells), _ptr(out.keys), _ptr(out.signs), cap,
                                   _ptr(out.round_stats), max_rounds, _ptr(out.summary), _ptr(ws),
                                   ws.numel(), _stream(stream)), "iblt_list_signed")
@@ -302,6 +314,11 @@ def batch_entries(tables: list[BatchTable], device) -> torch.Tensor:
     import numpy as np
     arr = np.zeros(len(tables), dtype=np.dtype(BATCH_ENTRY))
     for i, t in enumerate(tables):
+        d = t.desc
+        if not (2 <= d.r <= 8 and d.r <= d.ncells < (1 << 32)):
+            raise PeelError(f"batch table {i}: r={d.r}, ncells={d.ncells} out of range")
+        if t.cells.numel() < 4 * d.ncells or t.cells.data_ptr() % 32:
+            raise PeelError(f"batch table {i}: cells too small or not 32-byte aligned")
         arr[i] = (t.desc.ncells, t.desc.r, 0, t.desc.seed, t.cells.data_ptr(), t.keys.data_ptr(),
                   t.keys.numel(), t.round_stats.data_ptr(), t.summary.data_ptr())
     host = torch.from_numpy(arr.view(np.uint8).copy())
@@ -329,7 +346,7 @@ def iblt_list_batched(entries: torch.Tensor, ntables: int, max_cells: int, max_r
     ``lds_max_cells``: tables of at most this many cells are listed from LDS
     (None = the library default, IBLT_LDS_MAX_CELLS; 0 = never)."""
     if ws is None:
-        ws = workspace(iblt_list_batched_workspace(ntables, max_cells), entries.device)
+        ws = _call_ws(iblt_list_batched_workspace(ntables, max_cells), entries.device, stream)
     sched = BatchSchedule(block_threads,
                           IBLT_LDS_MAX_CELLS if lds_max_cells is None else lds_max_cells)
     _check(lib().iblt_list_batched(_ptr(entries), ntables, max_cells, max_rounds, C.byref(sched),

@@ -38,7 +38,8 @@ struct DeviceInfo {
   int id = -1;
   int cus = 0;
   int blocks_per_cu_cap = 0;         // PEEL_BLOCKS_PER_CU, 0 = occupancy only
-  uint64_t barrier_limit_ticks = 0;  // PEEL_BARRIER_TIMEOUT_MS of device wall clock (10 s)
+  uint64_t wall_khz = 0;             // device wall clock rate
+  uint64_t team_limit_ticks = 0;     // longest wait while a persistent team forms (10 s)
   uint64_t team_quiet_ticks = 0;     // PEEL_TEAM_QUIET_US of device wall clock (5 us)
   bool debug = false;                // PEEL_DEBUG: launch shapes on stderr
 };
@@ -65,9 +66,8 @@ inline const DeviceInfo &device_info() {
     (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
     if (khz <= 0) khz = 100000;  // 100 MHz
     d.cus = cus > 0 ? cus : 1;
-    long ms = env_long("PEEL_BARRIER_TIMEOUT_MS", 10000);
-    if (ms < 1) ms = 1;
-    d.barrier_limit_ticks = (uint64_t)khz * (uint64_t)ms;
+    d.wall_khz = (uint64_t)khz;
+    d.team_limit_ticks = (uint64_t)khz * 10000ull;
     long us = env_long("PEEL_TEAM_QUIET_US", 5);
     if (us < 1) us = 1;
     d.team_quiet_ticks = (uint64_t)khz * (uint64_t)us / 1000ull + 1;
@@ -77,6 +77,16 @@ inline const DeviceInfo &device_info() {
     d.id = dev;
   }
   return d;
+}
+
+// Device wall-clock ticks a device-wide barrier waits before the call gives
+// up and reports PEEL_FLAG_TIMEOUT: PEEL_BARRIER_TIMEOUT_MS (default 10000),
+// read at every call.  0 makes a barrier give up at its first poll that finds
+// it still closed; every workgroup then leaves its kernel at its next barrier,
+// which is how the tests reach the give-up path with every kernel ending.
+inline uint64_t barrier_limit_ticks() {
+  const long ms = env_long("PEEL_BARRIER_TIMEOUT_MS", 10000);
+  return device_info().wall_khz * (uint64_t)(ms < 0 ? 0 : ms);
 }
 
 // Workgroups of `kernel` (kBlock threads) that fit on the device at once.

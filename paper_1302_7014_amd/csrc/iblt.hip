@@ -31,13 +31,6 @@
 namespace peel {
 namespace {
 
-#ifndef PEEL_LDS_QUEUE
-#define PEEL_LDS_QUEUE 4096
-#endif
-constexpr int kQueue = PEEL_LDS_QUEUE;
-constexpr int kDenseItems = 4;  // cells per thread in the dense pass
-constexpr int kDenseTile = kBlock * kDenseItems;
-
 struct Hash {
   uint64_t base[8];
   uint64_t size[8];
@@ -422,6 +415,7 @@ struct ListArgs {
   ListCtrl *ctrl;
   uint64_t limit;
   uint64_t quiet;
+  uint64_t team_limit;
   uint32_t ncells;
   uint32_t max_rounds;
   uint32_t cb;
@@ -491,7 +485,7 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
 
   ListCtrl *ctrl = a.ctrl;
   uint32_t slot, T;
-  if (!team_join(&ctrl->team, a.quiet, a.limit, &slot, &T)) return;
+  if (!team_join(&ctrl->team, a.quiet, a.team_limit, &slot, &T)) return;
   const uint32_t tid = threadIdx.x;
   const uint64_t gtid = (uint64_t)slot * kLT + tid;
   const uint64_t gsize = (uint64_t)T * kLT;
@@ -680,7 +674,7 @@ __global__ void __launch_bounds__(kLT) k_list_sub(ListArgs a) {
 
   ListCtrl *ctrl = a.ctrl;
   uint32_t slot, T;
-  if (!team_join(&ctrl->team, a.quiet, a.limit, &slot, &T)) return;
+  if (!team_join(&ctrl->team, a.quiet, a.team_limit, &slot, &T)) return;
   const uint32_t tid = threadIdx.x;
   const uint64_t gtid = (uint64_t)slot * kLT + tid;
   const uint64_t gsize = (uint64_t)T * kLT;
@@ -1176,6 +1170,12 @@ __global__ void __launch_bounds__(NT)
     __syncthreads();
     if (ti >= ntables) return;
     const iblt_batch_entry e = entries[ti];
+    if (e.desc.r < 2 || e.desc.r > 8 || e.desc.ncells < e.desc.r || e.desc.ncells > max_cells ||
+        !e.cells || (reinterpret_cast<uintptr_t>(e.cells) & 31u)) {
+      // a bad entry is skipped: listing it could overrun this workgroup's scratch
+      if (e.summary && threadIdx.x < 8) e.summary[threadIdx.x] = threadIdx.x == 3 ? PEEL_FLAG_EINVAL : 0u;
+      continue;
+    }
     const Hash h = make_hash(e.desc);
     const uint32_t N = static_cast<uint32_t>(e.desc.ncells);
     if constexpr (LDS) {
@@ -1472,7 +1472,8 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
   a.stats = round_stats;
   a.signs = out_signs;
   a.signed_list = signed_list ? 1u : 0u;
-  a.limit = device_info().barrier_limit_ticks;
+  a.limit = barrier_limit_ticks();
+  a.team_limit = device_info().team_limit_ticks;
   a.quiet = device_info().team_quiet_ticks;
   a.ncells = static_cast<uint32_t>(desc->ncells);
   a.max_rounds = max_rounds;

@@ -107,6 +107,7 @@ struct PeelArgs {
   uint64_t m;
   uint64_t limit;
   uint64_t quiet;
+  uint64_t team_limit;
   uint32_t n;
   uint32_t k;
   uint32_t max_rounds;
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
 
   PeelCtrl *ctrl = a.ctrl;
   uint32_t slot, T;
-  if (!team_join(&ctrl->team_own, a.quiet, a.limit, &slot, &T)) return;
+  if (!team_join(&ctrl->team_own, a.quiet, a.team_limit, &slot, &T)) return;
   const uint32_t n = a.n;
   // vertex ranges start on 32-vertex boundaries, so bitmap slices do not share words
   const uint32_t Vb = ((n + T - 1) / T + 31u) & ~31u;
@@ -459,10 +460,12 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       __syncthreads();
       sorted_send(claims, nc, (uint32_t)m, Eb, T, a.qclaim);
     }
-    // The barrier sums |F_t| and, in subtables mode, the waiting bits (high word).
+    // The barrier sums |F_t| and, in subtables mode, the number of workgroups
+    // that still hold waiting bits (high word).  The barrier carries 48 bits:
+    // |F_t| <= n < 2^32 and at most kOwnMaxT workgroups keep the sum below 2^43.
     pend -= sub ? fcnt : 0u;
     uint64_t tot;
-    const uint64_t mine = sub ? ((uint64_t)pend << 32 | fcnt) : (uint64_t)fcnt;
+    const uint64_t mine = sub ? ((uint64_t)(pend != 0u) << 32 | fcnt) : (uint64_t)fcnt;
     if (!sum_barrier(&ctrl->bar, T, slot, mine, &epoch, a.limit, &tot, ctrl->stamp)) return;
     const uint64_t vt = sub ? (tot & 0xffffffffull) : tot;
     const uint64_t waiting = sub ? (tot >> 32) : 0u;
@@ -723,7 +726,7 @@ __global__ void __launch_bounds__(kBlock) k_peel_persistent(PeelArgs a) {
   if (__hip_atomic_load(&ctrl->mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kModeGlobal)
     return;
   uint32_t slot, nblocks;
-  if (!team_join(&ctrl->team_glob, a.quiet, a.limit, &slot, &nblocks)) return;
+  if (!team_join(&ctrl->team_glob, a.quiet, a.team_limit, &slot, &nblocks)) return;
   const uint64_t gtid = (uint64_t)slot * kBlock + threadIdx.x;
   const uint64_t gsize = (uint64_t)nblocks * kBlock;
   // Subtables mode: the list of round t holds every waiting vertex; those whose
@@ -962,7 +965,8 @@ peel_status peel_run(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n, 
   a.n = n;
   a.k = k;
   a.max_rounds = max_rounds;
-  a.limit = device_info().barrier_limit_ticks;
+  a.limit = barrier_limit_ticks();
+  a.team_limit = device_info().team_limit_ticks;
   a.quiet = device_info().team_quiet_ticks;
   const char *engine = std::getenv("PEEL_ENGINE");
   a.force_global = (engine && std::strcmp(engine, "global") == 0) ? 1u : 0u;

@@ -58,6 +58,7 @@ def gpu_peel(n: int, edges: np.ndarray, k: int, max_rounds: int = 4096, subtable
         "deg": host_u32(out.deg)[:n],
         "V": stats[:R, 0].copy(), "E": stats[:R, 1].copy(), "stats": stats,
         "rounds": R, "edge_rounds": int(summ[1]), "flags": int(summ[2]), "core": int(summ[3]),
+        "team": int(summ[4]),
     }
 
 

@@ -249,3 +249,116 @@ def test_config_batched_sample(which):
     assert left_cold <= 0.01 * (len(tables) - len(hot))
     if hot:
         assert left_hot >= 0.5 * len(hot)
+
+
+def _oracle_groups(N, r, ts, k, max_rounds, cap):
+    """The oracle's listing of one table: (summary-like tuple, K, groups, final table)."""
+    o_tab = native.iblt_insert(N, r, ts, k)
+    o = native.iblt_list_rounds(o_tab, max_rounds=max_rounds, out_cap=cap)
+    return o, o_tab
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("which", ["main", "partial"])
+def test_config_batched_every_table(which):
+    # Every one of the 4096 tables of the batched workload (and of the partial
+    # batch) against the oracle round by round -- per-round sorted key sets,
+    # K_t, rounds, summary, final cells -- and against its own plain iblt_list.
+    # The oracle runs on host threads (the C oracle releases the GIL).
+    need_gpu()
+    import concurrent.futures as cf
+    spec = configs.batched_main() if which == "main" else configs.batched_partial()
+    draw = spec.draw(1)
+    order = sorted(range(len(draw)), key=lambda i: -draw[i][0])
+    maxr = 256
+    tables, pristine = [], []
+    say("every table", which, "inserting")
+    for i in order:
+        N, m, ks, ts = draw[i]
+        d = pk.iblt_desc(N, spec.r, ts)
+        cells = pk.iblt_table(N, "cuda")
+        pk.iblt_insert(d, cells, gen.distinct_keys_torch(m, ks, "cuda"))
+        tables.append(pk.batch_table(d, cells, maxr))
+        pristine.append(cells.clone())
+    ent = pk.batch_entries(tables, "cuda")
+    torch.cuda.synchronize()
+    say("every table", which, "batched launch")
+    pk.iblt_list_batched(ent, len(tables), max(x[0] for x in draw), maxr)
+    torch.cuda.synchronize()
+    # the plain per-table listing of a copy of each table
+    plain = []
+    for t, p in zip(tables, pristine):
+        lo = pk.iblt_list(t.desc, p, max_rounds=maxr)
+        plain.append(lo)
+    torch.cuda.synchronize()
+    say("every table", which, "plain launches done; oracle on host threads")
+
+    def check(j):
+        i = order[j]
+        N, m, ks, ts = draw[i]
+        t = tables[j]
+        s, K, groups = _result(t)
+        o, o_tab = _oracle_groups(N, spec.r, ts, gen.distinct_keys(m, ks), maxr, t.keys.numel())
+        bad = []
+        if int(s[1]) != o.rounds or not np.array_equal(K, o.K):
+            bad.append("rounds")
+        if any(not np.array_equal(a, b) for a, b in zip(groups, o.per_round())):
+            bad.append("keys")
+        count, ksum, hsum, ok = table_to_numpy(t.cells)
+        if not (ok and np.array_equal(count, o_tab.count) and np.array_equal(ksum, o_tab.key_sum)
+                and np.array_equal(hsum, o_tab.hash_sum)):
+            bad.append("cells")
+        if int(s[0]) != o.keys.size or int(s[2]) != m - o.keys.size or int(s[3]) != 0:
+            bad.append("summary")
+        # plain iblt_list on the same table: same summary, rounds and key sets
+        ps = plain[j].summary.cpu().numpy()
+        pK = host_u64(plain[j].round_stats)[: int(ps[1])]
+        pk_ = host_u64(plain[j].keys)[: int(ps[0])]
+        if not (np.array_equal(ps[:4], s[:4]) and np.array_equal(pK, K)):
+            bad.append("plain summary")
+        off = 0
+        for kk, g in zip(K.tolist(), groups):
+            if not np.array_equal(np.sort(pk_[off: off + kk]), g):
+                bad.append("plain keys")
+                break
+            off += kk
+        return j, bad, int(s[2]) > 0
+
+    fails, left = [], 0
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        for n_done, (j, bad, kept) in enumerate(ex.map(check, range(len(tables))), 1):
+            if bad:
+                fails.append((j, bad))
+            left += kept
+            if n_done % 512 == 0:
+                say("every table", which, n_done, "checked,", len(fails), "mismatches")
+    assert fails == []
+    say("every table", which, "tables that kept a core:", left)
+
+
+def test_bad_entries_are_skipped_and_flagged():
+    # An entry with r out of range, more cells than max_cells, or misaligned
+    # cells is not listed; its summary says PEEL_FLAG_EINVAL and the other
+    # tables of the launch are listed as usual.
+    need_gpu()
+    specs = _specs(6, 8, lo=8, hi=11, rs=(3,))
+    tables, keys, pristine = _make_tables(specs, 64)
+    ent = pk.batch_entries(tables, "cuda")
+    raw = ent.cpu().numpy().view(np.dtype(pk.binding.BATCH_ENTRY)).copy()
+    raw[1]["r"] = 9
+    raw[3]["ncells"] = 1 << 20  # beyond max_cells below
+    raw[4]["cells"] += 8        # not 32-byte aligned
+    bad_ent = torch.from_numpy(raw.view(np.uint8).copy()).cuda()
+    maxc = max(x[0] for x in specs)
+    for i in (1, 3, 4):
+        tables[i].summary.fill_(-1)
+    say("bad batch entries")
+    pk.iblt_list_batched(bad_ent, len(tables), maxc, 64)
+    torch.cuda.synchronize()
+    for i, (t, k, p) in enumerate(zip(tables, keys, pristine)):
+        s = t.summary.cpu().numpy()
+        if i in (1, 3, 4):
+            assert s.tolist() == [0, 0, 0, pk.FLAG_EINVAL, 0, 0, 0, 0]
+            assert torch.equal(t.cells, p)  # untouched
+        else:
+            _check_against_oracle(t, k, 64)

@@ -155,13 +155,14 @@ def test_corrupt_cell():
     check_table(cells, t)
 
 
-def test_config_iblt_full_size():
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_config_iblt_full_size(seed):
     # 2^24 cells, r = 3, 10,296,982 keys: every key comes back, round by round as the oracle.
     need_gpu()
     spec = configs.iblt_main()
-    keys = spec.keys(1)
-    say(spec.name)
-    g, o = check_list(spec.ncells, spec.r, spec.table_seed(1), keys)
+    keys = spec.keys(seed)
+    say(spec.name, "seed", seed)
+    g, o = check_list(spec.ncells, spec.r, spec.table_seed(seed), keys)
     assert g["listed"] == spec.nkeys and g["left"] == 0
     assert np.array_equal(np.sort(np.concatenate(g["groups"])), np.sort(keys))
 

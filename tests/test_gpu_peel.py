@@ -254,3 +254,45 @@ def test_full_size_k3_n4M(which):
     say(spec.name)
     res = gpu_peel(spec.n, e, spec.k)
     _check_against_oracle(spec.n, e, spec.k, res)
+
+
+@pytest.mark.parametrize("seed", [2, 3, 4, 5])
+@pytest.mark.parametrize("c", [0.70, 0.85])
+def test_full_size_more_seeds(c, seed):
+    # n = 2^24, r = 4, k = 2 below and above the threshold, further seeds
+    need_gpu()
+    spec = configs.kcore_sweep(c)
+    e = spec.edges(seed)
+    say(spec.name, "seed", seed)
+    res = gpu_peel(spec.n, e, spec.k)
+    assert res["flags"] == 0
+    _check_against_oracle(spec.n, e, spec.k, res)
+
+
+@pytest.mark.parametrize("seed", [2, 3, 4, 5])
+@pytest.mark.parametrize("which", ["lo", "hi"])
+def test_full_size_k3_more_seeds(which, seed):
+    need_gpu()
+    spec = configs.kcore_k3(which)
+    e = spec.edges(seed)
+    say(spec.name, "seed", seed)
+    res = gpu_peel(spec.n, e, spec.k)
+    assert res["flags"] == 0
+    _check_against_oracle(spec.n, e, spec.k, res)
+
+
+def test_build_atomic_path_large_n():
+    # n > 2^26: hg_build takes its per-incidence atomic path, and the peel its
+    # global engine (a workgroup's vertex range no longer fits in LDS).
+    need_gpu()
+    n, m, r = (1 << 26) + 4099, 300_000, 3
+    e = gen.gnm_edges(n, m, r, 31)
+    # a few vertices of high degree, and ids at both ends of the range
+    e[:40, 0] = n - 1
+    e[40:80, 1] = 0
+    e[80:95, 2] = 12345
+    say("build atomic path", n, m)
+    res = gpu_peel(n, e, 2)
+    assert res["flags"] == 0
+    _check_csr(n, e, res)
+    _check_against_oracle(n, e, 2, res)

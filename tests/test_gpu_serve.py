@@ -69,3 +69,33 @@ def test_request_over_budget_is_rejected():
     srv = ContinuousServer(4 << 20, _fill, max_cells=1 << 20)
     done = srv.run(reqs + [big])
     assert [q.rid for q in srv.rejected] == [99] and len(done) == 5
+
+
+@pytest.mark.timeout(600)
+def test_mix_with_large_tables_equals_alone_and_oracle():
+    # Tables of 2^12 .. 2^22 cells (a third of them 2^18 and more, the binned
+    # fill and the large lanes): each result in the mix equals the request
+    # served alone and the oracle's listing, round by round.
+    need_gpu()
+    mix = _requests(36, 2000.0, 29, lo=12, hi=22)
+    big = sum(q.ncells >= 1 << 18 for q in mix)
+    assert big >= 10
+    budget = 768 << 20  # the three largest tables at once at most
+    say("serve mix, large tables", len(mix), big)
+    srv = ContinuousServer(budget, _fill, max_cells=1 << 22, keep_keys=True)
+    done = srv.run(mix)
+    assert len(done) == len(mix) and not srv.rejected
+    assert srv.arena.peak <= budget and srv.large >= big
+    fifo = FifoServer(budget, _fill, keep_keys=True, max_cells=1 << 22)
+    alone = {q.rid: q for q in fifo.run(_requests(36, 0.0, 29, lo=12, hi=22))}
+    for q in sorted(done, key=lambda q: q.rid):
+        a = alone[q.rid]
+        assert np.array_equal(q.summary[:4], a.summary[:4])
+        ga, gm = _groups(a), _groups(q)
+        assert len(ga) == len(gm) and all(np.array_equal(x, y) for x, y in zip(ga, gm))
+        k = gen.distinct_keys(q.nkeys, q.key_seed)
+        o = native.iblt_list_rounds(native.iblt_insert(q.ncells, q.r, q.table_seed, k),
+                                    max_rounds=256)
+        assert int(q.summary[0]) == o.keys.size and int(q.summary[1]) == o.rounds
+        assert all(np.array_equal(x, y) for x, y in zip(gm, o.per_round()))
+    say("serve mix, large tables: all equal")

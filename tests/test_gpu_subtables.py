@@ -94,3 +94,33 @@ def test_full_size_r4_n16M(c):
     # the k-core is the one the plain rounds reach
     plain = native.peel_rounds(spec.n, e, spec.k)
     assert np.array_equal(o.vertex_round == 0, plain.vertex_round == 0)
+
+
+def test_empty_subround_while_a_full_workgroup_waits():
+    # Regression: one owner workgroup holds 2^16 vertices waiting for a later
+    # subround (all of its range, in subtable 1) while subround 1 removes
+    # nothing anywhere.  The run must go on to subround 2 and remove them.
+    need_gpu()
+    import torch
+    T = torch.cuda.get_device_properties(0).multi_processor_count
+    n, r, k = 1 << 24, 3, 2
+    Vb = ((n + T - 1) // T + 31) & ~31
+    base1, base2 = gen.subtable_bases(n, r)[1:3]
+    s = (base1 + Vb - 1) // Vb
+    assert (s + 1) * Vb <= base2
+    iso = np.arange(s * Vb, (s + 1) * Vb, dtype=np.uint32)
+    rest = np.setdiff1d(np.arange(n, dtype=np.uint32), iso)
+    rng = np.random.default_rng(5)
+    rng.shuffle(rest)
+    whole = rest.size % 3 == 0
+    rest = rest[: rest.size // 3 * 3].reshape(-1, 3)
+    # every other vertex lies in two copies of one edge: degree 2, in the 2-core
+    e = np.concatenate([rest, rest]).astype(np.uint32)
+    say("subtables: empty subround, one workgroup waiting", n, e.shape, Vb)
+    res = gpu_peel(n, e, k, subtables=True)
+    assert res["flags"] == 0
+    o = _check(n, e, k, res)
+    if whole:
+        assert o.rounds == 2 and (o.vertex_round[iso] == 2).all()
+    if res["team"] == T:
+        assert Vb == iso.size
