@@ -348,6 +348,32 @@ peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32_t ntables,
                               const iblt_batch_schedule *sched, void *ws, size_t ws_bytes,
                               void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batched
+ * listing of iblt_list_batched, same arguments, same per-table results, with
+ * no workspace argument.  Its scratch (the batch's ticket counter and two
+ * max_cells-entry cell lists per workgroup) is one static device array of
+ * 64 MiB + 4 KiB that the library holds on each device it runs on until the
+ * process ends; it calls no allocator.  Its address is looked up on the
+ * device's first call.
+ *
+ *   max_cells     at most IBLT_NOALLOC_MAX_CELLS, else PEEL_ENOSPC (nothing
+ *                 runs); tables beyond it go through iblt_list_batched.
+ *   Other arguments as iblt_list_batched.  At most 512 workgroups run.
+ * Every call on one device shares that device's array, and it keeps the last
+ * call's contents (the ticket counter is cleared by a kernel at the start of
+ * each call, so the call can be graph-captured).  Calls that overlap on one
+ * device -- on different streams, or from different host threads -- race on
+ * it and must be serialised by the caller.  PEEL_EHIP if the array's address
+ * cannot be looked up.
+ */
+#define IBLT_NOALLOC_MAX_CELLS 16384u
+
+peel_status iblt_list_batched_noalloc(const iblt_batch_entry *entries, uint32_t ntables,
+                                      uint64_t max_cells, uint32_t max_rounds,
+                                      const iblt_batch_schedule *sched, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,7 @@ EXPORTS = ("peel_strerror", "peel_abi_version", "hg_build_workspace", "hg_build"
            "iblt_update_workspace", "iblt_update",
            "iblt_delete", "iblt_list_workspace", "iblt_list", "iblt_list_subtables",
            "iblt_list_signed",
-           "iblt_list_batched_workspace", "iblt_list_batched")
+           "iblt_list_batched_workspace", "iblt_list_batched", "iblt_list_batched_noalloc")
 
 _lib = None
 
@@ -77,9 +77,11 @@ def lib() -> C.CDLL:
         L.iblt_list_batched_workspace.argtypes = [u32, u64]
         L.iblt_list_batched_workspace.restype = sz
         L.iblt_list_batched.argtypes = [P, u32, u64, u32, C.POINTER(BatchSchedule), P, sz, P]
+        L.iblt_list_batched_noalloc.argtypes = [P, u32, u64, u32, C.POINTER(BatchSchedule), P]
         for f in ("hg_build", "peel_kcore", "peel_kcore_subtables", "iblt_insert", "iblt_delete",
                   "iblt_update",
-                  "iblt_list", "iblt_list_subtables", "iblt_list_signed", "iblt_list_batched"):
+                  "iblt_list", "iblt_list_subtables", "iblt_list_signed", "iblt_list_batched",
+                  "iblt_list_batched_noalloc"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -351,3 +353,19 @@ def iblt_list_batched(entries: torch.Tensor, ntables: int, max_cells: int, max_r
                           IBLT_LDS_MAX_CELLS if lds_max_cells is None else lds_max_cells)
     _check(lib().iblt_list_batched(_ptr(entries), ntables, max_cells, max_rounds, C.byref(sched),
                                    _ptr(ws), ws.numel(), _stream(stream)), "iblt_list_batched")
+
+
+IBLT_NOALLOC_MAX_CELLS = 16384
+
+
+def iblt_list_batched_noalloc(entries: torch.Tensor, ntables: int, max_cells: int,
+                              max_rounds: int, block_threads: int = 0,
+                              lds_max_cells: int | None = None, stream=None) -> None:
+    """``iblt_list_batched`` without a workspace: the library's own static
+    device scratch serves (max_cells <= IBLT_NOALLOC_MAX_CELLS).  Allocates
+    nothing; calls that overlap on one device race on that scratch."""
+    sched = BatchSchedule(block_threads,
+                          IBLT_LDS_MAX_CELLS if lds_max_cells is None else lds_max_cells)
+    _check(lib().iblt_list_batched_noalloc(_ptr(entries), ntables, max_cells, max_rounds,
+                                           C.byref(sched), _stream(stream)),
+           "iblt_list_batched_noalloc")

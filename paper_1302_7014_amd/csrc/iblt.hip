@@ -1558,10 +1558,24 @@ extern "C" size_t iblt_list_batched_workspace(uint32_t ntables, uint64_t max_cel
   return batched_ws_bytes(ntables, max_cells, batched_grid(ntables));
 }
 
-extern "C" peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32_t ntables,
-                                         uint64_t max_cells, uint32_t max_rounds,
-                                         const iblt_batch_schedule *sched, void *ws,
-                                         size_t ws_bytes, void *stream) {
+namespace peel {
+
+// Scratch of iblt_list_batched_noalloc: the batch's control block and the
+// per-workgroup candidate lists, in place of a caller workspace.  One copy per
+// device, held until the process ends; every call on a device shares it.
+// It holds IBLT_NOALLOC_MAX_CELLS-cell lists for kNoAllocGrid workgroups.
+constexpr uint32_t kNoAllocGrid = 512;
+constexpr size_t kNoAllocBytes =
+    4096 + (size_t)kNoAllocGrid * 2 * IBLT_NOALLOC_MAX_CELLS * sizeof(uint32_t);
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+// grid_cap: at most this many workgroups (0 = no cap).  Each workgroup lists
+// whole tables, so the grid changes the schedule, never the results.
+peel_status batched_run(const iblt_batch_entry *entries, uint32_t ntables, uint64_t max_cells,
+                        uint32_t max_rounds, const iblt_batch_schedule *sched, void *ws,
+                        size_t ws_bytes, void *stream, uint32_t grid_cap = 0) {
   if ((ntables && !entries) || max_rounds == 0 || max_cells >= (1ull << 32) || !ws)
     return PEEL_EINVAL;
   iblt_batch_schedule sc{512u, kLdsCells, {0u, 0u}};
@@ -1570,17 +1584,20 @@ extern "C" peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32
   if (sc.block_threads != 256 && sc.block_threads != 512 && sc.block_threads != 1024)
     return PEEL_EINVAL;
   if (sc.lds_max_cells > kLdsCells || sc.reserved[0] || sc.reserved[1]) return PEEL_EINVAL;
-  const uint32_t grid = batched_grid(ntables);
+  uint32_t grid = batched_grid(ntables);
+  if (grid_cap && grid > grid_cap) grid = grid_cap;
   if (ws_bytes < batched_ws_bytes(ntables, max_cells, grid)) return PEEL_ENOSPC;
   if (ntables == 0) return PEEL_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   BatchCtrl *ctrl = static_cast<BatchCtrl *>(ws);
-  uint32_t *scratch = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + align_up(sizeof(BatchCtrl)));
+  uint32_t *lists = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + align_up(sizeof(BatchCtrl)));
+  // the ticket counter starts at zero: cleared by a kernel, not a memset, so
+  // that the call can be captured in a graph
   hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(64), 0, s, ctrl);
   const uint32_t lm = sc.lds_max_cells;
 #define PEEL_BATCH_LAUNCH(NT, L) \
   hipLaunchKernelGGL((k_list_batched<NT, L>), dim3(grid), dim3(NT), 0, s, entries, ntables, \
-                     max_rounds, ctrl, scratch, max_cells, lm)
+                     max_rounds, ctrl, lists, max_cells, lm)
   switch (sc.block_threads) {
     case 256:
       if (lm) PEEL_BATCH_LAUNCH(256, true); else PEEL_BATCH_LAUNCH(256, false);
@@ -1595,4 +1612,42 @@ extern "C" peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32
 #undef PEEL_BATCH_LAUNCH
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current (each device holds its own copy at its own
+// address; the host-side name is only a stand-in).  Null if the lookup fails.
+void *noalloc_scratch() {
+  static std::mutex mu;
+  static void *addr[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    addr[dev] = p;
+  }
+  return addr[dev];
+}
+
+}  // namespace
+}  // namespace peel
+
+extern "C" peel_status iblt_list_batched(const iblt_batch_entry *entries, uint32_t ntables,
+                                         uint64_t max_cells, uint32_t max_rounds,
+                                         const iblt_batch_schedule *sched, void *ws,
+                                         size_t ws_bytes, void *stream) {
+  return batched_run(entries, ntables, max_cells, max_rounds, sched, ws, ws_bytes, stream);
+}
+
+extern "C" peel_status iblt_list_batched_noalloc(const iblt_batch_entry *entries,
+                                                 uint32_t ntables, uint64_t max_cells,
+                                                 uint32_t max_rounds,
+                                                 const iblt_batch_schedule *sched, void *stream) {
+  if (max_cells > IBLT_NOALLOC_MAX_CELLS) return PEEL_ENOSPC;
+  void *ws = noalloc_scratch();
+  if (!ws) return PEEL_EHIP;
+  return batched_run(entries, ntables, max_cells, max_rounds, sched, ws, kNoAllocBytes, stream,
+                     kNoAllocGrid);
 }

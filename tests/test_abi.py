@@ -119,3 +119,13 @@ def test_binned_update_is_checked_on_the_host(L):
     assert L.iblt_update(C.byref(d), dummy, dummy, nk, 1, None, 1 << 30, None) == pk.binding.PEEL_EINVAL
     assert L.iblt_update(C.byref(d), dummy, dummy, nk, 1, dummy, 1024, None) == pk.binding.PEEL_ENOSPC
     assert L.iblt_update(C.byref(d), dummy, dummy, 0, 1, None, 0, None) == pk.binding.PEEL_OK
+
+
+def test_noalloc_batched_limit_is_checked_on_the_host(L):
+    # past its static scratch the no-allocation listing refuses before any launch
+    src = open(os.path.join(ROOT, "include", "peel.h")).read()
+    lim = int(re.search(r"#define IBLT_NOALLOC_MAX_CELLS (\d+)u", src).group(1))
+    assert lim == pk.IBLT_NOALLOC_MAX_CELLS
+    dummy = C.c_void_p(0x1000)
+    assert L.iblt_list_batched_noalloc(dummy, 4, lim + 1, 8, None, None) == pk.binding.PEEL_ENOSPC
+    assert L.iblt_list_batched_noalloc(dummy, 4, 1 << 40, 8, None, None) == pk.binding.PEEL_ENOSPC
