@@ -9,7 +9,7 @@ events on the stream the kernels run on), the CPU oracle timed on the host
 on the same workload, and secondary measurements (peel alone, IBLT insert and
 list at 2^24 cells).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--sweep]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-sweep] ...
 """
 from __future__ import annotations
 
@@ -151,6 +151,7 @@ def bench_kcore(spec, steps, warmup, subtables=False):
         raise RuntimeError(f"peel flags {int(summ[2])}")
     m_rem = int((er != 0).sum())
     return {
+        "vr": vr, "er": er,
         "wall_s": wall, "m_removed": m_rem, "rounds": int(summ[0]), "edge_rounds": int(summ[1]),
         "core_vertices": int(summ[3]),
         "build_ms": float(np.mean(tb.ms)), "peel_ms": float(np.mean(tp.ms)),
@@ -159,6 +160,41 @@ def bench_kcore(spec, steps, warmup, subtables=False):
         "peel_bytes": peel_bytes(n, r, e_host, deg0, vr, er),
         "build_bytes": build_bytes(n, m, r), "edges_host": e_host,
     }
+
+
+def bench_k2_xor(spec, steps, warmup, ref):
+    """peel_k2_xor (no CSR: degrees and edge-id XORs per vertex) on the same
+    workload: the whole k = 2 step in one call, its outputs compared with the
+    build + peel_kcore run's on the device."""
+    dev = torch.device("cuda", 0)
+    e = torch.from_numpy(ref["edges_host"].view(np.int32)).to(dev).view(spec.m, spec.r)
+    n, m, r = spec.n, spec.m, spec.r
+    max_rounds = 4096
+    out = pk.PeelOut(torch.empty(n, dtype=torch.int32, device=dev),
+                     torch.empty(n, dtype=torch.int32, device=dev),
+                     torch.empty(m, dtype=torch.int32, device=dev),
+                     torch.empty(2 * max_rounds, dtype=torch.int64, device=dev),
+                     torch.empty(8, dtype=torch.int32, device=dev))
+    ws = pk.workspace(pk.peel_k2_xor_workspace(n, m, r), dev)
+    t = Timer()
+    for _ in range(warmup):
+        pk.peel_k2_xor(e, n, max_rounds=max_rounds, out=out, ws=ws)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        with t:
+            pk.peel_k2_xor(e, n, max_rounds=max_rounds, out=out, ws=ws)
+    t.collect()
+    summ = out.summary.cpu().numpy().view(np.uint32)
+    same = (np.array_equal(out.vertex_round.cpu().numpy().view(np.uint32), ref["vr"])
+            and np.array_equal(out.edge_round.cpu().numpy().view(np.uint32), ref["er"])
+            and int(summ[0]) == ref["rounds"])
+    ms = float(np.median(t.ms))
+    return {"workload": spec.name, "step": "peel_k2_xor (degree/XOR build + peel)",
+            "step_ms": ms, "step_ms_p10_p90": [float(np.percentile(t.ms, 10)),
+                                                float(np.percentile(t.ms, 90))],
+            "edges_per_s": ref["m_removed"] / (ms * 1e-3), "rounds": int(summ[0]),
+            "flags": int(summ[2]), "equal_to_build_peel": bool(same),
+            "vs_build_peel_ms": ref["build_ms"] + ref["peel_ms"]}
 
 
 def bench_iblt(spec, reps):
@@ -215,7 +251,10 @@ def bench_iblt(spec, reps):
         "insert_keys_per_s": spec.nkeys / (ins * 1e-3),
         "list_keys_per_s": listed / (lst * 1e-3),
         "insert_gbs": iblt_insert_bytes(spec.nkeys, spec.r) / (ins * 1e-3) / 1e9,
+        "insert_binned_gbs": iblt_insert_bytes(spec.nkeys, spec.r) / (upd * 1e-3) / 1e9,
         "list_gbs": iblt_list_bytes(spec.ncells, spec.r, listed) / (lst * 1e-3) / 1e9,
+        "list_frac_of_peak": iblt_list_bytes(spec.ncells, spec.r, listed) / (lst * 1e-3) / 1e9
+                             / HBM_PEAK_GBS,
         "subtables": {"list_ms": sub_ms, "listed": int(sub_s[0]), "subrounds": int(sub_s[1]),
                       "list_keys_per_s": int(sub_s[0]) / (sub_ms * 1e-3)},
     }
@@ -453,7 +492,30 @@ def cpu_baseline(spec, e_host):
                       f"{spec.name} ({spec.m} edges), {dt:.2f} s", "host": host_cpu(),
             "serial_queue": {"value": mq / dq, "unit": "edges/s", "cores": 1,
                              "sample": f"one full run of oracle peel_queue on the same "
-                                       f"workload, {dq:.2f} s"}}
+                                       f"workload, {dq:.2f} s"},
+            "all_cores": cpu_all_cores(spec, e_host)}
+
+
+def cpu_all_cores(spec, e_host, cap=16):
+    """The same single-threaded oracle run on every usable host core at once: one
+    independent peel_rounds of the workload per thread (the C oracle releases the
+    interpreter lock), so the aggregate is the host's throughput for this
+    workload with the oracle as it stands."""
+    import concurrent.futures as cf
+    from oracle import native  # CPU-baseline leg only
+    p = max(1, min(cap, len(os.sched_getaffinity(0))))
+
+    def one(_):
+        o = native.peel_rounds(spec.n, e_host, spec.k)
+        return int((o.edge_round != 0).sum())
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=p) as ex:
+        done = sum(ex.map(one, range(p)))
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "edges/s", "cores": p, "kind": "oracle",
+            "sample": f"{p} concurrent oracle peel_rounds runs of {spec.name}, one per thread, "
+                      f"{dt:.2f} s wall"}
 
 
 def main():
@@ -463,11 +525,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-iblt", action="store_true")
-    ap.add_argument("--sweep", action="store_true", help="also time every c of the n=2^24 sweep")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the other c of the n=2^24 sweep and the near-threshold points")
     ap.add_argument("--no-subtables", action="store_true",
                     help="skip the subtables peel and the k = 3 peels (profiles of the main "
                          "workload alone)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-xor", action="store_true", help="skip the CSR-free k = 2 peel")
     ap.add_argument("--iblt-main", action="store_true",
                     help="of the IBLT workloads, only the 2^24-cell main one (profiles of one shape)")
     ap.add_argument("--no-serve", action="store_true")
@@ -512,6 +576,9 @@ def main():
     extra["stream_copy_gbs"] = copy_gbs
     extra["peel_frac_of_copy"] = extra["peel_gbs"] / copy_gbs
     extra["build_frac_of_copy"] = extra["build_gbs"] / copy_gbs
+    if not args.no_xor:
+        log("CSR-free k = 2 peel")
+        extra["csr_free_k2"] = bench_k2_xor(spec, args.steps, args.warmup, kc)
     if not args.no_subtables:
         # the paper's own schedule (peeling with subtables) on the same workload
         sb = bench_kcore(spec, max(3, args.steps // 2), 1, subtables=True)
@@ -548,15 +615,18 @@ def main():
     if not args.no_serve:
         log("served decoding")
         extra["serve"] = bench_serve(configs.served_main(), 1000, args.serve_requests, 500)
-    if args.sweep:
+    if not args.no_sweep:
+        log("peel sweep over c at n = 2^24")
         sw = []
         for c in configs.SWEEP_C + configs.NEAR_C:
             s2 = configs.kcore_sweep(c)
             r2 = bench_kcore(s2, max(3, args.steps // 4), 1)
-            sw.append({"workload": s2.name, "m": s2.m, "rounds": r2["rounds"],
-                       "m_removed": r2["m_removed"], "peel_ms": r2["peel_ms"],
-                       "build_ms": r2["build_ms"],
-                       "peel_gbs": r2["peel_bytes"] / (r2["peel_ms"] * 1e-3) / 1e9})
+            gbs = r2["peel_bytes"] / (r2["peel_ms"] * 1e-3) / 1e9
+            sw.append({"workload": s2.name, "c": c, "m": s2.m, "rounds": r2["rounds"],
+                       "m_removed": r2["m_removed"], "core_vertices": r2["core_vertices"],
+                       "peel_ms": r2["peel_ms"], "build_ms": r2["build_ms"],
+                       "peel_edges_per_s": r2["m_removed"] / (r2["peel_ms"] * 1e-3),
+                       "peel_gbs": gbs, "peel_frac_of_peak": gbs / HBM_PEAK_GBS})
         extra["sweep"] = sw
     line = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,

@@ -57,6 +57,9 @@ typedef int32_t peel_status;
                                 /* the call's other outputs are then undefined  */
 #define PEEL_FLAG_EINVAL 0x20u  /* a batch entry was rejected (r, size, or      */
                                 /* alignment); that table was left untouched    */
+#define PEEL_FLAG_ETEAM 0x40u   /* peel_k2_xor: the resident team that formed   */
+                                /* was too small to hold n vertices in LDS;     */
+                                /* nothing was peeled (peel_kcore has no limit) */
 
 /* Human-readable name of a status code; never NULL. */
 const char *peel_strerror(peel_status s);
@@ -146,6 +149,39 @@ peel_status peel_kcore_subtables(const uint32_t *edges, uint64_t m, uint32_t r, 
                                  uint32_t *deg, uint32_t *vertex_round, uint32_t *edge_round,
                                  uint64_t *round_stats, uint32_t max_rounds, uint32_t *summary,
                                  void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Peeling to the 2-core without vertex -> edge lists (Section 5,
+ * "Motivation": listing an IBLT is peeling its hypergraph, and a pure cell --
+ * a vertex of degree one -- names its one item by its key sum).  Every vertex
+ * keeps its degree and the XOR of the ids of its alive incident edges, so at
+ * k = 2 a vertex of F_t that still holds an edge names it directly.  The same
+ * rounds as peel_kcore with k = 2, and the same outputs, bit for bit; no
+ * hg_build is needed.  An edge taken in round t is taken by its vertex of
+ * F_t in the lowest slot of its row (F_t is published as a bitmap each
+ * round), so it dies once with no compare-and-swap.
+ *
+ *   edges, m, r, n   as for hg_build (k is 2).
+ *   deg              (device, out) n uint32: the core degree of each core
+ *                    vertex, 0 for every removed vertex (the initial degrees
+ *                    are computed here).
+ *   vertex_round, edge_round, round_stats, max_rounds, summary
+ *                    as for peel_kcore.  summary[2] also carries
+ *                    PEEL_FLAG_ERANGE (an id >= n; such ids are ignored) and
+ *                    PEEL_FLAG_ETEAM.
+ *   ws               (device) ws_bytes >= peel_k2_xor_workspace(n, m, r):
+ *                    the XORs (4n bytes), the round's messages (8 r m bytes
+ *                    and about 8 (r-1) n of staging), the frontier (4n) and
+ *                    its bitmap (n/8), and the degree build's scratch.
+ * The vertices are held in LDS by a team of resident workgroups of at most
+ * 98304 vertices each: with fewer than n / 98304 workgroups resident the call
+ * peels nothing and sets PEEL_FLAG_ETEAM (peel_kcore has no such limit).
+ */
+size_t peel_k2_xor_workspace(uint32_t n, uint64_t m, uint32_t r);
+peel_status peel_k2_xor(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n,
+                        uint32_t *deg, uint32_t *vertex_round, uint32_t *edge_round,
+                        uint64_t *round_stats, uint32_t max_rounds, uint32_t *summary,
+                        void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Invertible Bloom Lookup Table (Section 5).                                */

@@ -23,12 +23,13 @@ LIB_PATH = os.path.join(HERE, "libpeel.so")
 
 PEEL_OK, PEEL_EINVAL, PEEL_ERANGE, PEEL_ENOSPC, PEEL_EROUNDS, PEEL_ECORRUPT, PEEL_EHIP = (
     0, -1, -2, -3, -4, -5, -6)
-FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT, FLAG_EINVAL = (
-    0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
+FLAG_ERANGE, FLAG_EROUNDS, FLAG_ENOSPC, FLAG_ECORRUPT, FLAG_TIMEOUT, FLAG_EINVAL, FLAG_ETEAM = (
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40)
 
 # Every symbol include/peel.h declares.
 EXPORTS = ("peel_strerror", "peel_abi_version", "hg_build_workspace", "hg_build",
-           "peel_kcore_workspace", "peel_kcore", "peel_kcore_subtables", "iblt_insert",
+           "peel_kcore_workspace", "peel_kcore", "peel_kcore_subtables",
+           "peel_k2_xor_workspace", "peel_k2_xor", "iblt_insert",
            "iblt_update_workspace", "iblt_update",
            "iblt_delete", "iblt_list_workspace", "iblt_list", "iblt_list_subtables",
            "iblt_list_signed",
@@ -64,6 +65,9 @@ def lib() -> C.CDLL:
         L.peel_kcore_workspace.restype = sz
         L.peel_kcore.argtypes = [P, u64, u32, u32, u32, P, P, P, P, P, P, u32, P, P, sz, P]
         L.peel_kcore_subtables.argtypes = L.peel_kcore.argtypes
+        L.peel_k2_xor_workspace.argtypes = [u32, u64, u32]
+        L.peel_k2_xor_workspace.restype = sz
+        L.peel_k2_xor.argtypes = [P, u64, u32, u32, P, P, P, P, u32, P, P, sz, P]
         L.iblt_insert.argtypes = [C.POINTER(IbltDesc), P, P, u64, P]
         L.iblt_list_workspace.argtypes = [C.POINTER(IbltDesc)]
         L.iblt_list_workspace.restype = sz
@@ -78,7 +82,8 @@ def lib() -> C.CDLL:
         L.iblt_list_batched_workspace.restype = sz
         L.iblt_list_batched.argtypes = [P, u32, u64, u32, C.POINTER(BatchSchedule), P, sz, P]
         L.iblt_list_batched_noalloc.argtypes = [P, u32, u64, u32, C.POINTER(BatchSchedule), P]
-        for f in ("hg_build", "peel_kcore", "peel_kcore_subtables", "iblt_insert", "iblt_delete",
+        for f in ("hg_build", "peel_kcore", "peel_kcore_subtables", "peel_k2_xor", "iblt_insert",
+                  "iblt_delete",
                   "iblt_update",
                   "iblt_list", "iblt_list_subtables", "iblt_list_signed", "iblt_list_batched",
                   "iblt_list_batched_noalloc"):
@@ -189,6 +194,31 @@ def peel_kcore(edges: torch.Tensor, n: int, k: int, csr: Csr, max_rounds: int = 
               _ptr(out.deg), _ptr(out.vertex_round), _ptr(out.edge_round),
               _ptr(out.round_stats), max_rounds, _ptr(out.summary), _ptr(ws),
               ws.numel(), _stream(stream)), "peel_kcore_subtables" if subtables else "peel_kcore")
+    return out
+
+
+def peel_k2_xor_workspace(n: int, m: int, r: int) -> int:
+    return int(lib().peel_k2_xor_workspace(n, m, r))
+
+
+def peel_k2_xor(edges: torch.Tensor, n: int, max_rounds: int = 4096,
+                out: PeelOut | None = None, ws: torch.Tensor | None = None,
+                stream=None) -> PeelOut:
+    """Peel to the 2-core with no CSR (degrees and edge-id XORs per vertex);
+    the same outputs as ``peel_kcore`` with k = 2.  ``out.deg`` receives the
+    final degrees."""
+    m, r = edges.shape
+    dev = edges.device
+    if out is None:
+        out = PeelOut(_empty(n, torch.int32, dev), _empty(n, torch.int32, dev),
+                      _empty(m, torch.int32, dev), _empty(2 * max_rounds, torch.int64, dev),
+                      _empty(8, torch.int32, dev))
+    if ws is None:
+        ws = _call_ws(peel_k2_xor_workspace(n, m, r), dev, stream)
+    _check(lib().peel_k2_xor(_ptr(edges), m, r, n, _ptr(out.deg), _ptr(out.vertex_round),
+                             _ptr(out.edge_round), _ptr(out.round_stats), max_rounds,
+                             _ptr(out.summary), _ptr(ws), ws.numel(), _stream(stream)),
+           "peel_k2_xor")
     return out
 
 

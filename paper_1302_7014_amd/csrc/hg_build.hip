@@ -27,6 +27,7 @@
 // build falls back to one device atomic per incidence for the degrees and
 // another for the cursors.
 #include "common.hpp"
+#include "degxor.hpp"
 #include "host.hpp"
 #include "scan.hpp"
 
@@ -287,14 +288,16 @@ __global__ void __launch_bounds__(kBT)
 // (edge - first edge of its tile) << kBinShift | (vertex - first vertex of the
 // bucket), and the bucket's runs are in tile order, so a pair's tile is the
 // last tile whose run starts at or before the pair's place.
-template <typename P>
+// XOR: degrees and, in place of the lists, the XOR of each vertex's incident
+// edge ids (written to inc[v], n entries); offsets and maxdeg are not used.
+template <typename P, bool XOR = false>
 __global__ void __launch_bounds__(kBT)
     k_bin_build(const P *__restrict__ pairs, uint32_t n, uint32_t nb, uint64_t ntiles,
                 const uint32_t *__restrict__ hist8, const uint32_t *total, uint32_t *offsets,
                 uint32_t *inc, uint32_t *deg, uint32_t *maxdeg) {
   constexpr bool kP4 = sizeof(P) == 4;
   __shared__ uint32_t cnt[kBinV + kBinV / 32];
-  __shared__ uint32_t stage[kStageCap];
+  __shared__ uint32_t stage[XOR ? kBinV : kStageCap];  // XOR: the bucket's edge-id XORs
   __shared__ uint32_t bnd[kP4 ? kMaxTiles4 + 1 : 1];           // start of each tile's run
   __shared__ uint16_t blk[kP4 ? kStageCap / kBlk : 1];         // tile of every kBlk-th place
   __shared__ uint32_t lds[kBT / kWave + 1];
@@ -304,6 +307,8 @@ __global__ void __launch_bounds__(kBT)
   const uint32_t v0 = b << kBinShift;
   const uint32_t nv = (n - v0) < (uint32_t)kBinV ? (n - v0) : (uint32_t)kBinV;
   for (uint32_t i = threadIdx.x; i < (uint32_t)(kBinV + kBinV / 32); i += kBT) cnt[i] = 0;
+  if constexpr (XOR)
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kBinV; i += kBT) stage[i] = 0;
   if (kP4) {
     for (uint32_t t = threadIdx.x; t < (uint32_t)ntiles; t += kBT) bnd[t] = hist8[(uint64_t)b * ntiles + t];
     if (threadIdx.x == 0) bnd[ntiles] = end;
@@ -383,6 +388,20 @@ __global__ void __launch_bounds__(kBT)
       }
     }
   };
+  if constexpr (XOR) {
+    __syncthreads();  // the tile table is complete before edge() reads it
+    for_pairs([&](uint32_t p, P x) {
+      const uint32_t v = vloc(x);
+      atomicAdd(&cnt[pad(v)], 1u);
+      atomicXor(&stage[v], edge(p, x));
+    });
+    __syncthreads();
+    for (uint32_t v = threadIdx.x; v < nv; v += kBT) {
+      deg[v0 + v] = cnt[pad(v)];
+      inc[v0 + v] = stage[v];
+    }
+    return;
+  }
   for_pairs([&](uint32_t, P x) { atomicAdd(&cnt[pad(vloc(x))], 1u); });
   __syncthreads();
   // exclusive scan of cnt[0..kBinV): kPer consecutive counts per thread
@@ -497,7 +516,7 @@ size_t build_ws_bytes(uint32_t n, uint64_t m, uint32_t r) {
          2 * align_up((z.pairs ? z.pairs : 1) * 8) + align_up((z.nb + 4) * 4) + 512;
 }
 
-template <int R>
+template <int R, bool XOR = false>
 peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t *offsets,
                          uint32_t *inc, uint32_t *deg, uint32_t *info, Carver &c, hipStream_t s) {
   const Sizes z = sizes(n, m, R);
@@ -519,7 +538,7 @@ peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t
     uint32_t *pairs4 = reinterpret_cast<uint32_t *>(pairs);
     hipLaunchKernelGGL(k_bin_scatter4<R>, dim3(z.ntiles), dim3(kBT), 0, s, edges, m, n,
                        (uint32_t)z.nb, z.ntiles, hist8, pairs4);
-    hipLaunchKernelGGL(k_bin_build<uint32_t>, dim3(z.nb), dim3(kBT), 0, s, pairs4, n,
+    hipLaunchKernelGGL((k_bin_build<uint32_t, XOR>), dim3(z.nb), dim3(kBT), 0, s, pairs4, n,
                        (uint32_t)z.nb, z.ntiles, hist8, total8, offsets, inc, deg, info + 1);
     PEEL_HIP_TRY(hipGetLastError());
     return PEEL_OK;
@@ -540,7 +559,7 @@ peel_status build_binned(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t
                        hist8, z.nb, 0u);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(kBlock), 0, s, total8, (uint64_t)1, 0u);
   }
-  hipLaunchKernelGGL(k_bin_build<uint64_t>, dim3(z.nb), dim3(kBT), 0, s, pairs2, n, (uint32_t)z.nb,
+  hipLaunchKernelGGL((k_bin_build<uint64_t, XOR>), dim3(z.nb), dim3(kBT), 0, s, pairs2, n, (uint32_t)z.nb,
                      z.ntiles ? z.ntiles : 1, hist8, total8, offsets, inc, deg, info + 1);
   PEEL_HIP_TRY(hipGetLastError());
   return PEEL_OK;
@@ -574,7 +593,60 @@ peel_status build(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t *offse
                    : build_atomic<R>(edges, m, n, offsets, inc, deg, info, c, s);
 }
 
+// deg[v] += 1 and xr[v] ^= e for every incidence (e, v) with v < n (n > 2^26).
+template <int R>
+__global__ void __launch_bounds__(kBlock)
+    k_count_xor(const uint32_t *__restrict__ edges, uint64_t m, uint32_t n, uint32_t *deg,
+                uint32_t *xr, uint32_t *info) {
+  for (uint64_t e = blockIdx.x * (uint64_t)kBlock + threadIdx.x; e < m;
+       e += (uint64_t)gridDim.x * kBlock) {
+    const uint32_t *row = edges + e * R;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint32_t v = row[j];
+      if (v < n) {
+        atomicAdd(&deg[v], 1u);
+        atomicXor(&xr[v], static_cast<uint32_t>(e));
+      } else {
+        atomicOr(&info[0], PEEL_FLAG_ERANGE);
+      }
+    }
+  }
+}
+
+template <int R>
+peel_status degxor(const uint32_t *edges, uint64_t m, uint32_t n, uint32_t *deg, uint32_t *xr,
+                   uint32_t *info, Carver &c, hipStream_t s) {
+  if (binned(n)) return build_binned<R, true>(edges, m, n, nullptr, xr, deg, info, c, s);
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s,
+                     deg, (uint64_t)n, 0u);
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s,
+                     xr, (uint64_t)n, 0u);
+  if (m)
+    hipLaunchKernelGGL(k_count_xor<R>, dim3(grid_for(m, kBlock, 1u << 16)), dim3(kBlock), 0, s,
+                       edges, m, n, deg, xr, info);
+  PEEL_HIP_TRY(hipGetLastError());
+  return PEEL_OK;
+}
+
 }  // namespace
+
+size_t degxor_ws_bytes(uint32_t n, uint64_t m, uint32_t r) { return build_ws_bytes(n, m, r); }
+
+peel_status degxor_build(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n, uint32_t *deg,
+                         uint32_t *xr, uint32_t *info, void *ws, hipStream_t s) {
+  Carver c(ws);
+  switch (r) {
+    case 2: return degxor<2>(edges, m, n, deg, xr, info, c, s);
+    case 3: return degxor<3>(edges, m, n, deg, xr, info, c, s);
+    case 4: return degxor<4>(edges, m, n, deg, xr, info, c, s);
+    case 5: return degxor<5>(edges, m, n, deg, xr, info, c, s);
+    case 6: return degxor<6>(edges, m, n, deg, xr, info, c, s);
+    case 7: return degxor<7>(edges, m, n, deg, xr, info, c, s);
+    default: return degxor<8>(edges, m, n, deg, xr, info, c, s);
+  }
+}
+
 }  // namespace peel
 
 using namespace peel;

@@ -71,3 +71,24 @@ def table_to_numpy(cells: torch.Tensor):
     hs = h[:, 2].view(np.uint64).copy()
     reserved_ok = bool((res0 == 0).all() and (h[:, 3] == 0).all())
     return count, ks, hs, reserved_ok
+
+
+def gpu_peel_xor(n: int, edges: np.ndarray, max_rounds: int = 4096):
+    """peel_k2_xor on the GPU (no CSR); returns numpy results like gpu_peel."""
+    e = dev_u32(edges.reshape(-1, edges.shape[1]) if edges.size else
+                np.zeros((0, edges.shape[1]), np.uint32))
+    e = e.view(edges.shape[0], edges.shape[1])
+    out = pk.peel_k2_xor(e, n, max_rounds=max_rounds)
+    torch.cuda.synchronize()
+    m = edges.shape[0]
+    summ = host_u32(out.summary)
+    stats = host_u64(out.round_stats)[: 2 * max_rounds].reshape(max_rounds, 2)
+    R = int(summ[0])
+    return {
+        "vertex_round": host_u32(out.vertex_round)[:n],
+        "edge_round": host_u32(out.edge_round)[:m],
+        "deg": host_u32(out.deg)[:n],
+        "V": stats[:R, 0].copy(), "E": stats[:R, 1].copy(), "stats": stats,
+        "rounds": R, "edge_rounds": int(summ[1]), "flags": int(summ[2]), "core": int(summ[3]),
+        "team": int(summ[4]),
+    }
