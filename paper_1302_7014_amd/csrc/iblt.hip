@@ -910,12 +910,103 @@ __global__ void k_list_finish(const ListCtrl *ctrl, uint32_t r, uint64_t *summar
 // table at a time (tables taken in the given order from a shared ticket), the
 // round barrier being the workgroup barrier.
 
+// Deletes keys[0, K) -- key i listed from its cell own[i] -- from a table that
+// this workgroup alone writes, with no device atomic: the other r - 1 cells of
+// a key take one plain 32-byte read-modify-write each.  kXU keys per thread at
+// a time, one subtable after another (a key has one cell per subtable, and the
+// subtables are disjoint).  In each pass, an LDS hash set of cell indices lets
+// the first update of a cell apply and defers the others to the next pass, so
+// the updates of one cell apply one after another and each sees the count the
+// one before left: a cell is pushed when its count goes from 2 to 1, exactly
+// as with atomics.  The cell a key was listed from held that key alone, so it
+// is cleared with a plain store and no other update reaches it.
+constexpr int kXU = 2;  // keys per thread per apply chunk
+constexpr uint32_t kNoCell = 0xffffffffu;
+
+template <int NT>
+constexpr uint32_t kApplySet = 2u * kXU * NT;  // hash slots: at most half of them are used
+
+// hset: LDS of kApplySet<NT> words.
+template <int R, int NT, typename Push>
+__device__ void apply_exclusive(const Hash &h, iblt_cell *cells, const uint64_t *keys,
+                                const uint32_t *own, uint32_t K, uint32_t *hset, Push push) {
+  constexpr uint32_t kSet = kApplySet<NT>;
+  constexpr uint32_t kBits = kSet == 1024 ? 10 : kSet == 2048 ? 11 : 12;
+  static_assert((1u << kBits) == kSet, "NT is 256, 512 or 1024");
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t k0 = 0; k0 < K; k0 += kXU * NT) {
+    uint64_t x[kXU], hx[kXU];
+    uint32_t co[kXU];
+    bool live[kXU];
+#pragma unroll
+    for (int u = 0; u < kXU; ++u) {
+      const uint32_t i = k0 + (uint32_t)u * NT + tid;
+      live[u] = i < K;
+      x[u] = live[u] ? keys[i] : 0ull;
+      co[u] = live[u] ? own[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kXU; ++u) {
+      hx[u] = check_of(h, x[u]);
+      if (live[u]) clear_cell(cells + co[u]);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      uint32_t c[kXU];
+      bool pend[kXU];
+#pragma unroll
+      for (int u = 0; u < kXU; ++u) {
+        c[u] = cell_of(h, j, x[u]);
+        pend[u] = live[u] && c[u] != co[u];
+      }
+      for (;;) {
+        for (uint32_t q = tid; q < kSet; q += NT) hset[q] = kNoCell;
+        __syncthreads();
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < kXU; ++u) {
+          if (!pend[u]) continue;
+          uint32_t q = (c[u] * 0x9e3779b1u) >> (32 - kBits);
+          bool lead = false;
+          for (;;) {
+            const uint32_t old = atomicCAS(&hset[q], kNoCell, c[u]);
+            if (old == kNoCell) {
+              lead = true;
+              break;
+            }
+            if (old == c[u]) break;
+            q = (q + 1) & (kSet - 1);
+          }
+          if (!lead) {
+            any = true;  // this cell already has an update in this pass
+            continue;
+          }
+          uint4 *p = reinterpret_cast<uint4 *>(cells + c[u]);
+          uint4 a = p[0], b = p[1];
+          const int32_t old = static_cast<int32_t>(a.x);
+          a.x = static_cast<uint32_t>(old - 1);
+          a.z ^= static_cast<uint32_t>(x[u]);
+          a.w ^= static_cast<uint32_t>(x[u] >> 32);
+          b.x ^= static_cast<uint32_t>(hx[u]);
+          b.y ^= static_cast<uint32_t>(hx[u] >> 32);
+          p[0] = a;
+          p[1] = b;
+          if (old == 2) push(c[u]);
+          pend[u] = false;
+        }
+        if (!__syncthreads_or(any)) break;
+      }
+    }
+  }
+}
+
 // Lists one table with one NT-thread workgroup.  cand and own are scratch of
 // ncells entries each.  Writes the table's outputs like iblt_list.
 template <int R, int NT>
 __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, uint64_t *out,
                                  uint64_t out_cap, uint64_t *stats, uint32_t max_rounds,
-                                 uint64_t *summary, uint32_t *cand, uint32_t *own) {
+                                 uint64_t *summary, uint32_t *cand, uint32_t *own,
+                                 uint32_t *hset) {
   __shared__ uint32_t s_k, s_c, s_bad, s_flags;
   __shared__ unsigned long long s_sum;
   const uint32_t tid = threadIdx.x;
@@ -964,8 +1055,8 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
       s_c = 0;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < K; i += NT)
-      delete_key<R>(h, cells, out[listed + i], own[i], [&](uint32_t c) { cand[atomicAdd(&s_c, 1u)] = c; });
+    apply_exclusive<R, NT>(h, cells, out + listed, own, K, hset,
+                           [&](uint32_t c) { cand[atomicAdd(&s_c, 1u)] = c; });
     __syncthreads();
     listed += K;
     const uint32_t nc = s_c;
@@ -1161,6 +1252,11 @@ __global__ void __launch_bounds__(NT)
                    BatchCtrl *ctrl, uint32_t *scratch, uint64_t max_cells, uint32_t lds_max) {
   __shared__ uint32_t s_t;
   __shared__ typename std::conditional<LDS, LdsTable, uint32_t>::type lt;
+  // the in-place apply's hash set: the LDS table's space when there is one
+  __shared__ uint32_t hset_own[LDS ? 1 : kApplySet<NT>];
+  static_assert(!LDS || sizeof(LdsTable) >= kApplySet<NT> * sizeof(uint32_t),
+                "the hash set fits in the LDS table");
+  uint32_t *hset = LDS ? reinterpret_cast<uint32_t *>(&lt) : hset_own;
   uint32_t *cand = scratch + (uint64_t)blockIdx.x * 2 * max_cells;
   uint32_t *own = cand + max_cells;
   for (;;) {
@@ -1196,13 +1292,13 @@ __global__ void __launch_bounds__(NT)
       }
     }
     switch (e.desc.r) {
-      case 2: list_table_block<2, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
-      case 3: list_table_block<3, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
-      case 4: list_table_block<4, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
-      case 5: list_table_block<5, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
-      case 6: list_table_block<6, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
-      case 7: list_table_block<7, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
-      default: list_table_block<8, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own); break;
+      case 2: list_table_block<2, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
+      case 3: list_table_block<3, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
+      case 4: list_table_block<4, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
+      case 5: list_table_block<5, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
+      case 6: list_table_block<6, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
+      case 7: list_table_block<7, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
+      default: list_table_block<8, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
     }
   }
 }
