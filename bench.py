@@ -301,6 +301,18 @@ def bench_signed(reps):
             "list_keys_per_s": int(s[0]) / (lst * 1e-3)}
 
 
+def _tuner_summary(rep):
+    """Per size class: tables, the chosen schedule, the fastest and slowest
+    candidate; and the whole-batch trials of the thread counts."""
+    out = {}
+    for cls, c in rep["classes"].items():
+        ms = [t["ms"] for t in c["trials"]]
+        out[cls] = {"tables": c["tables"], "choice": c["choice"], "best_ms": min(ms),
+                    "worst_ms": max(ms), "trials": c["trials"]}
+    out["combined"] = rep["combined"]
+    return out
+
+
 def bench_batched(spec, reps):
     """One launch for every table (block-per-table schedule) vs one iblt_list per table."""
     draw = spec.draw(1)
@@ -328,7 +340,7 @@ def bench_batched(spec, reps):
 
     # pick the schedule on this batch, then capture the batched call in a graph
     from paper_1302_7014_amd.autotune import tune_batched
-    sched, trials = tune_batched(tables, ent, maxc, 256, ws)
+    sched, tuner = tune_batched(tables, ent, maxc, 256, ws)
     log(f"batched schedule {sched}")
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -362,7 +374,7 @@ def bench_batched(spec, reps):
     return {
         "workload": spec.name, "tables": len(tables), "cells": int(sum(x[0] for x in draw)),
         "keys": nkeys, "listed": listed, "incomplete_tables": incomplete,
-        "schedule": sched, "tuner_trials": trials,
+        "schedule": sched, "tuner": _tuner_summary(tuner),
         "batched_graph_ms": bt, "plain_per_table_ms": pt, "speedup": pt / bt,
         "batched_keys_per_s": listed / (bt * 1e-3), "plain_keys_per_s": listed_plain / (pt * 1e-3),
         # the listing's algorithmic bytes summed over the tables (each table's
@@ -603,6 +615,8 @@ def main():
         extra["batched"] = bench_batched(configs.batched_main(), 3)
         log("batched IBLT listing, 5% of the tables above threshold")
         extra["batched_partial"] = bench_batched(configs.batched_partial(), 3)
+        log("batched IBLT listing, 16 tables of 2^20 cells")
+        extra["batched_few_large"] = bench_batched(configs.batched_few_large(), 3)
     if not args.no_iblt:
         log("IBLT 2^24 cells")
         extra["iblt"] = [bench_iblt(configs.iblt_main(), 5)]

@@ -342,21 +342,35 @@ peel_status iblt_list_subtables(const iblt_desc *desc, iblt_cell *cells, uint64_
  * order of `entries` from a shared counter and list each with workgroup-wide
  * barriers only.  Sorting `entries` by decreasing ncells balances the load.
  *
- * Two per-table schedules exist.  A table of at most `lds_max_cells` cells is
- * read once into the workgroup's local memory (LDS), listed there with LDS
- * atomics, and written back; a larger table is listed in place in device
- * memory.  Both give the same results.
+ * Three per-table schedules exist, chosen by size class:
+ *   - a table of at most `lds_max_cells` cells is read once into the
+ *     workgroup's local memory (LDS), listed there with LDS atomics, and
+ *     written back;
+ *   - a table of at least `tile_min_cells` cells (with tile_workgroups >= 2)
+ *     is listed by a team of tile_workgroups workgroups of the same launch:
+ *     member g detects the g-th slice of the cells in round 1 and then the
+ *     cells it pushed, keys leave the shared cells by device atomics, and a
+ *     barrier among the members (with the time limit of iblt_list's) ends
+ *     each half round;
+ *   - any other table is listed in place in device memory by one workgroup,
+ *     the table's only writer, with plain read-modify-writes of its cells.
+ * All give the same results.  A team takes tile_workgroups consecutive work
+ * units from the shared counter; members are only ever workgroups that are
+ * running, and at least tile_workgroups of them are, so a team always forms.
  *
  *   entries       (device) ntables descriptors; every pointer in them is
  *                 device memory and every table is disjoint from the others.
  *   max_cells     >= the largest ncells among the tables.
  *   max_rounds    >= 1, for every table (round_stats hold max_rounds each).
  *   sched         (host) the schedule, or NULL for the defaults (512 threads,
- *                 lds_max_cells = IBLT_LDS_MAX_CELLS).  block_threads must be
- *                 256, 512 or 1024 (0 = 512) and lds_max_cells at most
- *                 IBLT_LDS_MAX_CELLS, else PEEL_EINVAL.
- *   ws            (device) ws_bytes >= iblt_list_batched_workspace().
- * Each table's summary is written as iblt_list's ([4] = 1 workgroup).  An
+ *                 lds_max_cells = IBLT_LDS_MAX_CELLS, no teams).
+ *                 block_threads must be 256, 512 or 1024 (0 = 512),
+ *                 lds_max_cells at most IBLT_LDS_MAX_CELLS and tile_workgroups
+ *                 at most 64, else PEEL_EINVAL.
+ *   ws            (device) ws_bytes >= iblt_list_batched_workspace(), which
+ *                 covers every schedule.
+ * Each table's summary is written as iblt_list's ([4] = the workgroups that
+ * listed it; PEEL_FLAG_TIMEOUT if a team's barrier gave up).  An
  * entry with r outside 2..8, ncells < r, ncells > max_cells, or cells that are
  * null or not 32-byte aligned is not listed: its summary (if not null) gets
  * [3] = PEEL_FLAG_EINVAL and zeros elsewhere, and the other tables go on.
@@ -364,9 +378,10 @@ peel_status iblt_list_subtables(const iblt_desc *desc, iblt_cell *cells, uint64_
 #define IBLT_LDS_MAX_CELLS 2048u
 
 typedef struct iblt_batch_schedule {
-    uint32_t block_threads;  /* threads per workgroup: 256, 512, 1024; 0 = 512 */
-    uint32_t lds_max_cells;  /* tables this small are listed in LDS; 0 = none */
-    uint32_t reserved[2];    /* 0 */
+    uint32_t block_threads;   /* threads per workgroup: 256, 512, 1024; 0 = 512  */
+    uint32_t lds_max_cells;   /* tables this small are listed in LDS; 0 = none   */
+    uint32_t tile_min_cells;  /* tables at least this large are listed by a team */
+    uint32_t tile_workgroups; /* of this many workgroups (2..64); 0 or 1 = none  */
 } iblt_batch_schedule;
 
 typedef struct iblt_batch_entry {

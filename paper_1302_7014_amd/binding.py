@@ -365,22 +365,27 @@ IBLT_LDS_MAX_CELLS = 2048
 
 
 class BatchSchedule(C.Structure):
-    """iblt_batch_schedule: threads per workgroup and the LDS-resident size limit."""
+    """iblt_batch_schedule: threads per workgroup, the LDS-resident size limit,
+    and the team ("tile") schedule for large tables."""
     _fields_ = [("block_threads", C.c_uint32), ("lds_max_cells", C.c_uint32),
-                ("reserved", C.c_uint32 * 2)]
+                ("tile_min_cells", C.c_uint32), ("tile_workgroups", C.c_uint32)]
 
 
 def iblt_list_batched(entries: torch.Tensor, ntables: int, max_cells: int, max_rounds: int,
                       block_threads: int = 0, lds_max_cells: int | None = None,
+                      tile_min_cells: int = 0, tile_workgroups: int = 0,
                       ws: torch.Tensor | None = None, stream=None) -> None:
     """List every table of a batch in one launch (entries from ``batch_entries``).
 
     ``lds_max_cells``: tables of at most this many cells are listed from LDS
-    (None = the library default, IBLT_LDS_MAX_CELLS; 0 = never)."""
+    (None = the library default, IBLT_LDS_MAX_CELLS; 0 = never).  Tables of at
+    least ``tile_min_cells`` cells are listed by teams of ``tile_workgroups``
+    workgroups (0 or 1 = no teams)."""
     if ws is None:
         ws = _call_ws(iblt_list_batched_workspace(ntables, max_cells), entries.device, stream)
     sched = BatchSchedule(block_threads,
-                          IBLT_LDS_MAX_CELLS if lds_max_cells is None else lds_max_cells)
+                          IBLT_LDS_MAX_CELLS if lds_max_cells is None else lds_max_cells,
+                          tile_min_cells, tile_workgroups)
     _check(lib().iblt_list_batched(_ptr(entries), ntables, max_cells, max_rounds, C.byref(sched),
                                    _ptr(ws), ws.numel(), _stream(stream)), "iblt_list_batched")
 
@@ -390,12 +395,14 @@ IBLT_NOALLOC_MAX_CELLS = 16384
 
 def iblt_list_batched_noalloc(entries: torch.Tensor, ntables: int, max_cells: int,
                               max_rounds: int, block_threads: int = 0,
-                              lds_max_cells: int | None = None, stream=None) -> None:
+                              lds_max_cells: int | None = None, tile_min_cells: int = 0,
+                              tile_workgroups: int = 0, stream=None) -> None:
     """``iblt_list_batched`` without a workspace: the library's own static
     device scratch serves (max_cells <= IBLT_NOALLOC_MAX_CELLS).  Allocates
     nothing; calls that overlap on one device race on that scratch."""
     sched = BatchSchedule(block_threads,
-                          IBLT_LDS_MAX_CELLS if lds_max_cells is None else lds_max_cells)
+                          IBLT_LDS_MAX_CELLS if lds_max_cells is None else lds_max_cells,
+                          tile_min_cells, tile_workgroups)
     _check(lib().iblt_list_batched_noalloc(_ptr(entries), ntables, max_cells, max_rounds,
                                            C.byref(sched), _stream(stream)),
            "iblt_list_batched_noalloc")

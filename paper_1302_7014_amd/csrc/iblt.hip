@@ -1090,6 +1090,133 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
 }
 
 // ---------------------------------------------------------------------------
+// Team ("tile") schedule for large tables: Gt workgroups of the one launch list
+// one table together.  Member g takes cells [g N / Gt, (g+1) N / Gt) in round
+// 1, then the keys it found and the cells it pushed; the cells are shared, so
+// keys leave them with device atomics, and a barrier among the members (one
+// per table) ends each detect and each apply.  Same rounds, key sets and
+// summary as the single-workgroup schedules.
+struct TeamCtrl {
+  GridSync bar;
+  uint32_t kpos[2];            // keys found this round, by round parity
+  uint32_t flags;
+  uint32_t bad;
+  unsigned long long sum;      // counts of every cell at the start
+  uint32_t pad[6];
+};
+static_assert(sizeof(TeamCtrl) == 64, "one line per table");
+
+template <int R, int NT>
+__device__ void list_table_team(const Hash &h, iblt_cell *cells, uint32_t N, uint64_t *out,
+                                uint64_t out_cap, uint64_t *stats, uint32_t max_rounds,
+                                uint64_t *summary, uint32_t *cand, uint32_t *own, uint32_t g,
+                                uint32_t Gt, TeamCtrl *tc, uint64_t limit) {
+  __shared__ uint32_t s_k, s_c, s_bad, s_pos;
+  __shared__ unsigned long long s_sum;
+  const uint32_t tid = threadIdx.x;
+  if (g == 0)
+    for (uint32_t i = tid; i < max_rounds; i += NT) stats[i] = 0;
+  if (tid == 0) {
+    s_k = 0;
+    s_bad = 0;
+    s_sum = 0;
+  }
+  __syncthreads();
+  // round-1 detect over my slice of the cells
+  {
+    const uint32_t c0 = (uint32_t)((uint64_t)N * g / Gt), c1 = (uint32_t)((uint64_t)N * (g + 1) / Gt);
+    long long local = 0;
+    uint32_t bad = 0;
+    for (uint32_t c = c0 + tid; c < c1; c += NT) {
+      int32_t cnt;
+      uint64_t ks, hs;
+      load_cell(cells + c, &cnt, &ks, &hs);
+      local += cnt;
+      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) own[atomicAdd(&s_k, 1u)] = c;
+    }
+    if (bad) s_bad = 1;
+    atomicAdd(&s_sum, (unsigned long long)local);
+  }
+  uint64_t listed = 0;
+  uint32_t t = 1;
+  bool ok = true;
+  for (;; ++t) {
+    __syncthreads();
+    const uint32_t mine = s_k;
+    if (tid == 0) {
+      s_pos = atomicAdd(&tc->kpos[t & 1], mine);
+      if (t == 1) atomicAdd(&tc->sum, s_sum);
+      if (s_bad) atomicOr(&tc->bad, 1u);
+    }
+    // the keys go to out only once the round is known to fit; the cells
+    // still hold them until the apply, which starts after the barrier
+    if (!grid_barrier(&tc->bar, Gt, limit)) {
+      ok = false;
+      break;
+    }
+    const uint32_t K = atomic_load_u32(&tc->kpos[t & 1]);
+    if (K == 0) break;
+    if (t > max_rounds) {
+      if (g == 0 && tid == 0) atomicOr(&tc->flags, PEEL_FLAG_EROUNDS);
+      break;
+    }
+    if (listed + K > out_cap) {
+      if (g == 0 && tid == 0) atomicOr(&tc->flags, PEEL_FLAG_ENOSPC);
+      break;
+    }
+    if (g == 0 && tid == 0) {
+      stats[t - 1] = K;
+      // every member read last round's total before this barrier
+      __hip_atomic_store(&tc->kpos[(t + 1) & 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t base = (uint32_t)listed + s_pos;
+    for (uint32_t i = tid; i < mine; i += NT) {
+      int32_t cnt;
+      uint64_t ks, hs;
+      load_cell(cells + own[i], &cnt, &ks, &hs);
+      out[base + i] = ks;
+    }
+    if (tid == 0) s_c = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < mine; i += NT)
+      delete_key<R>(h, cells, out[base + i], own[i], [&](uint32_t c) { cand[atomicAdd(&s_c, 1u)] = c; });
+    listed += K;
+    if (!grid_barrier(&tc->bar, Gt, limit)) {
+      ok = false;
+      break;
+    }
+    const uint32_t nc = s_c;
+    if (tid == 0) s_k = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (uint32_t i = tid; i < nc; i += NT) {
+      const uint32_t c = cand[i];
+      int32_t cnt;
+      uint64_t ks, hs;
+      load_cell(cells + c, &cnt, &ks, &hs);
+      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) own[atomicAdd(&s_k, 1u)] = c;
+    }
+    if (bad) s_bad = 1;
+  }
+  // Every member stops at the same round (the totals are the team's), so
+  // member 0 writes the summary with no further barrier: the flags and counts
+  // it reads were all in before the barrier that ended the detect.
+  if (g == 0) {
+    if (tid == 0) {
+      const long long keys = (long long)atomic_load_u64(reinterpret_cast<uint64_t *>(&tc->sum)) / (long long)R;
+      summary[0] = listed;
+      summary[1] = t - 1 < max_rounds ? t - 1 : max_rounds;
+      summary[2] = (uint64_t)(keys - (long long)listed);
+      summary[3] = atomic_load_u32(&tc->flags) | (atomic_load_u32(&tc->bad) ? PEEL_FLAG_ECORRUPT : 0u) |
+                   (ok ? 0u : PEEL_FLAG_TIMEOUT);
+      summary[4] = Gt;
+      summary[5] = summary[6] = summary[7] = 0;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // LDS-resident schedule for small tables: the table is read once into the
 // workgroup's local memory (structure of arrays), every round's detect and
 // apply run on it with LDS atomics, and the final cells are written back.
@@ -1243,13 +1370,16 @@ __device__ void list_table_lds(const Hash &h, iblt_cell *cells, uint32_t N, uint
 
 struct BatchCtrl {
   uint32_t ticket;
-  uint32_t pad[63];
+  uint32_t units;  // work units: one per table, tile_workgroups per team table
+  uint32_t pad[62];
 };
 
+// first/teams: null when the team schedule is off (a work unit is then a table).
 template <int NT, bool LDS>
 __global__ void __launch_bounds__(NT)
     k_list_batched(const iblt_batch_entry *entries, uint32_t ntables, uint32_t max_rounds,
-                   BatchCtrl *ctrl, uint32_t *scratch, uint64_t max_cells, uint32_t lds_max) {
+                   BatchCtrl *ctrl, uint32_t *scratch, uint64_t max_cells, uint32_t lds_max,
+                   const uint32_t *first, TeamCtrl *teams, uint64_t limit) {
   __shared__ uint32_t s_t;
   __shared__ typename std::conditional<LDS, LdsTable, uint32_t>::type lt;
   // the in-place apply's hash set: the LDS table's space when there is one
@@ -1259,10 +1389,30 @@ __global__ void __launch_bounds__(NT)
   uint32_t *hset = LDS ? reinterpret_cast<uint32_t *>(&lt) : hset_own;
   uint32_t *cand = scratch + (uint64_t)blockIdx.x * 2 * max_cells;
   uint32_t *own = cand + max_cells;
+  __shared__ uint32_t s_g, s_gt;
   for (;;) {
-    if (threadIdx.x == 0) s_t = atomicAdd(&ctrl->ticket, 1u);
+    if (threadIdx.x == 0) {
+      const uint32_t u = atomicAdd(&ctrl->ticket, 1u);
+      uint32_t ti = u, g = 0, gt = 1;
+      if (first) {
+        // the table whose units hold unit u: the last i with first[i] <= u
+        uint32_t lo = 0, hi = ntables;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (first[mid] <= u) lo = mid; else hi = mid;
+        }
+        ti = u < first[ntables] ? lo : ntables;
+        if (ti < ntables) {
+          g = u - first[ti];
+          gt = first[ti + 1] - first[ti];
+        }
+      }
+      s_t = ti;
+      s_g = g;
+      s_gt = gt;
+    }
     __syncthreads();
-    const uint32_t ti = s_t;
+    const uint32_t ti = s_t, g = s_g, gt = s_gt;
     __syncthreads();
     if (ti >= ntables) return;
     const iblt_batch_entry e = entries[ti];
@@ -1274,6 +1424,24 @@ __global__ void __launch_bounds__(NT)
     }
     const Hash h = make_hash(e.desc);
     const uint32_t N = static_cast<uint32_t>(e.desc.ncells);
+    if (gt > 1) {
+#define PEEL_TEAM_CASE(RR)                                                                        \
+  case RR:                                                                                        \
+    list_table_team<RR, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds,     \
+                            e.summary, cand, own, g, gt, teams + ti, limit);                      \
+    break;
+      switch (e.desc.r) {
+        PEEL_TEAM_CASE(2)
+        PEEL_TEAM_CASE(3)
+        PEEL_TEAM_CASE(4)
+        PEEL_TEAM_CASE(5)
+        PEEL_TEAM_CASE(6)
+        PEEL_TEAM_CASE(7)
+        PEEL_TEAM_CASE(8)
+      }
+#undef PEEL_TEAM_CASE
+      continue;
+    }
     if constexpr (LDS) {
       if (N <= lds_max) {
 #define PEEL_LDS_CASE(RR) \
@@ -1303,8 +1471,38 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-__global__ void k_batch_init(BatchCtrl *ctrl) {
-  if (threadIdx.x == 0) ctrl->ticket = 0;
+// Clears the ticket; with the team schedule on, also gives each table its
+// work units (tile_workgroups for a table of at least tile_min cells, else 1),
+// their exclusive prefix in `first` (ntables + 1 entries), and a cleared
+// TeamCtrl per table.  One workgroup of kInitT threads.
+constexpr int kInitT = 1024;
+__global__ void __launch_bounds__(kInitT)
+    k_batch_init(BatchCtrl *ctrl, const iblt_batch_entry *entries, uint32_t ntables,
+                 uint32_t tile_min, uint32_t tile_g, uint32_t *first, TeamCtrl *teams) {
+  __shared__ uint32_t lds[kInitT / kWave + 1];
+  if (threadIdx.x == 0) {
+    ctrl->ticket = 0;
+    ctrl->units = ntables;
+  }
+  if (tile_g < 2) return;
+  uint32_t base = 0;
+  for (uint32_t i0 = 0; i0 < ntables; i0 += kInitT) {
+    const uint32_t i = i0 + threadIdx.x;
+    uint32_t u = 0;
+    if (i < ntables) {
+      u = entries[i].desc.ncells >= tile_min ? tile_g : 1u;
+      uint32_t *w = reinterpret_cast<uint32_t *>(teams + i);
+      for (int q = 0; q < (int)(sizeof(TeamCtrl) / 4); ++q) w[q] = 0;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<kInitT>(u, &tot, lds);
+    if (i < ntables) first[i] = base + ex;
+    base += tot;
+  }
+  if (threadIdx.x == 0) {
+    first[ntables] = base;
+    ctrl->units = base;
+  }
 }
 
 // ===========================================================================
@@ -1359,14 +1557,35 @@ peel_status launch_list(ListArgs &a, hipStream_t s, bool subtables) {
   return PEEL_OK;
 }
 
-size_t batched_ws_bytes(uint32_t ntables, uint64_t max_cells, uint32_t grid) {
-  (void)ntables;
-  return align_up(sizeof(BatchCtrl)) + align_up((uint64_t)grid * 2 * max_cells * 4);
+// Workspace: the control block, two max_cells lists per workgroup, then (for
+// the team schedule) the tables' first work units and their TeamCtrl.
+struct BatchLayout {
+  size_t ctrl, lists, first, teams, total;
+};
+
+BatchLayout batched_layout(uint32_t ntables, uint64_t max_cells, uint32_t grid) {
+  BatchLayout L{};
+  L.ctrl = align_up(sizeof(BatchCtrl));
+  L.lists = align_up((uint64_t)grid * 2 * max_cells * 4);
+  L.first = align_up(((uint64_t)ntables + 1) * 4);
+  L.teams = align_up((uint64_t)ntables * sizeof(TeamCtrl));
+  L.total = L.ctrl + L.lists + L.first + L.teams;
+  return L;
 }
 
-uint32_t batched_grid(uint32_t ntables) {
-  const uint32_t g = static_cast<uint32_t>(2 * device_info().cus);
-  return ntables < g ? (ntables ? ntables : 1) : g;
+constexpr uint32_t kTeamMax = 64;  // most workgroups in one team
+
+// Workgroups of a launch: two per CU, fewer for a batch with fewer tables (or,
+// with teams, fewer table units).  The workspace is sized for the most any
+// schedule launches.
+uint32_t batched_grid(uint32_t ntables, uint32_t tile_g = 1) {
+  const uint64_t g = 2ull * device_info().cus;
+  const uint64_t want = (uint64_t)(ntables ? ntables : 1) * (tile_g ? tile_g : 1);
+  return static_cast<uint32_t>(want < g ? want : g);
+}
+
+size_t batched_ws_bytes(uint32_t ntables, uint64_t max_cells, uint32_t grid) {
+  return batched_layout(ntables, max_cells, grid).total;
 }
 
 }  // namespace
@@ -1651,7 +1870,7 @@ extern "C" peel_status iblt_list_subtables(const iblt_desc *desc, iblt_cell *cel
 }
 
 extern "C" size_t iblt_list_batched_workspace(uint32_t ntables, uint64_t max_cells) {
-  return batched_ws_bytes(ntables, max_cells, batched_grid(ntables));
+  return batched_ws_bytes(ntables, max_cells, batched_grid(ntables, kTeamMax));
 }
 
 namespace peel {
@@ -1659,10 +1878,11 @@ namespace peel {
 // Scratch of iblt_list_batched_noalloc: the batch's control block and the
 // per-workgroup candidate lists, in place of a caller workspace.  One copy per
 // device, held until the process ends; every call on a device shares it.
-// It holds IBLT_NOALLOC_MAX_CELLS-cell lists for kNoAllocGrid workgroups.
+// It holds IBLT_NOALLOC_MAX_CELLS-cell lists for kNoAllocGrid workgroups and
+// 1 MiB for the team schedule's per-table arrays.
 constexpr uint32_t kNoAllocGrid = 512;
 constexpr size_t kNoAllocBytes =
-    4096 + (size_t)kNoAllocGrid * 2 * IBLT_NOALLOC_MAX_CELLS * sizeof(uint32_t);
+    4096 + (size_t)kNoAllocGrid * 2 * IBLT_NOALLOC_MAX_CELLS * sizeof(uint32_t) + (1u << 20);
 __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
@@ -1674,26 +1894,35 @@ peel_status batched_run(const iblt_batch_entry *entries, uint32_t ntables, uint6
                         size_t ws_bytes, void *stream, uint32_t grid_cap = 0) {
   if ((ntables && !entries) || max_rounds == 0 || max_cells >= (1ull << 32) || !ws)
     return PEEL_EINVAL;
-  iblt_batch_schedule sc{512u, kLdsCells, {0u, 0u}};
+  iblt_batch_schedule sc{512u, kLdsCells, 0u, 0u};
   if (sched) sc = *sched;
   if (sc.block_threads == 0) sc.block_threads = 512;
   if (sc.block_threads != 256 && sc.block_threads != 512 && sc.block_threads != 1024)
     return PEEL_EINVAL;
-  if (sc.lds_max_cells > kLdsCells || sc.reserved[0] || sc.reserved[1]) return PEEL_EINVAL;
-  uint32_t grid = batched_grid(ntables);
+  if (sc.lds_max_cells > kLdsCells || sc.tile_workgroups > kTeamMax) return PEEL_EINVAL;
+  const bool teams = sc.tile_workgroups >= 2 && sc.tile_min_cells >= 1;
+  const uint32_t tg = teams ? sc.tile_workgroups : 1u;
+  uint32_t grid = batched_grid(ntables, tg);
   if (grid_cap && grid > grid_cap) grid = grid_cap;
-  if (ws_bytes < batched_ws_bytes(ntables, max_cells, grid)) return PEEL_ENOSPC;
+  const BatchLayout L = batched_layout(ntables, max_cells, grid);
+  // the per-table arrays are needed only with teams
+  if (ws_bytes < (teams ? L.total : L.ctrl + L.lists)) return PEEL_ENOSPC;
   if (ntables == 0) return PEEL_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  BatchCtrl *ctrl = static_cast<BatchCtrl *>(ws);
-  uint32_t *lists = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + align_up(sizeof(BatchCtrl)));
-  // the ticket counter starts at zero: cleared by a kernel, not a memset, so
-  // that the call can be captured in a graph
-  hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(64), 0, s, ctrl);
+  char *base = static_cast<char *>(ws);
+  BatchCtrl *ctrl = reinterpret_cast<BatchCtrl *>(base);
+  uint32_t *lists = reinterpret_cast<uint32_t *>(base + L.ctrl);
+  uint32_t *first = teams ? reinterpret_cast<uint32_t *>(base + L.ctrl + L.lists) : nullptr;
+  TeamCtrl *tctrl = teams ? reinterpret_cast<TeamCtrl *>(base + L.ctrl + L.lists + L.first) : nullptr;
+  // the ticket counter (and the team arrays) start cleared by a kernel, not a
+  // memset, so that the call can be captured in a graph
+  hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(kInitT), 0, s, ctrl, entries, ntables,
+                     sc.tile_min_cells, tg, first, tctrl);
   const uint32_t lm = sc.lds_max_cells;
+  const uint64_t limit = barrier_limit_ticks();
 #define PEEL_BATCH_LAUNCH(NT, L) \
   hipLaunchKernelGGL((k_list_batched<NT, L>), dim3(grid), dim3(NT), 0, s, entries, ntables, \
-                     max_rounds, ctrl, lists, max_cells, lm)
+                     max_rounds, ctrl, lists, max_cells, lm, first, tctrl, limit)
   switch (sc.block_threads) {
     case 256:
       if (lm) PEEL_BATCH_LAUNCH(256, true); else PEEL_BATCH_LAUNCH(256, false);

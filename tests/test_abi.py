@@ -79,8 +79,7 @@ def test_batched_schedule_is_checked_on_the_host(L):
     for bt, lds in [(128, 0), (300, 0), (512, pk.IBLT_LDS_MAX_CELLS + 1)]:
         s = pk.BatchSchedule(bt, lds)
         assert L.iblt_list_batched(dummy, 4, 1000, 8, C.byref(s), dummy, 1 << 30, None) == pk.binding.PEEL_EINVAL
-    s = pk.BatchSchedule(512, 0)
-    s.reserved[0] = 1
+    s = pk.BatchSchedule(512, 0, 1 << 18, 65)  # teams of more than 64 workgroups
     assert L.iblt_list_batched(dummy, 4, 1000, 8, C.byref(s), dummy, 1 << 30, None) == pk.binding.PEEL_EINVAL
     assert L.iblt_list_batched(dummy, 4, 1000, 0, None, dummy, 1 << 30, None) == pk.binding.PEEL_EINVAL
 

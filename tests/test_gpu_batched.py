@@ -362,3 +362,135 @@ def test_bad_entries_are_skipped_and_flagged():
             assert torch.equal(t.cells, p)  # untouched
         else:
             _check_against_oracle(t, k, 64)
+
+
+@pytest.mark.parametrize("threads,lds,tmin,G", [(256, 0, 1 << 12, 2), (512, pk.IBLT_LDS_MAX_CELLS, 1 << 13, 4),
+                                                (1024, 0, 1 << 12, 16), (1024, pk.IBLT_LDS_MAX_CELLS, 1 << 14, 64)])
+def test_team_schedule_matches_oracle(threads, lds, tmin, G):
+    # tables of at least tmin cells are listed by teams of G workgroups; every
+    # table, whatever its schedule, equals the oracle round by round
+    need_gpu()
+    specs = _specs(40, 5, lo=8, hi=16)
+    specs.sort(key=lambda x: -x[0])
+    tables, keys, _ = _make_tables(specs, 256)
+    ent = pk.batch_entries(tables, "cuda")
+    say("team schedule", threads, lds, tmin, G)
+    pk.iblt_list_batched(ent, len(tables), max(x[0] for x in specs), 256, block_threads=threads,
+                         lds_max_cells=lds, tile_min_cells=tmin, tile_workgroups=G)
+    torch.cuda.synchronize()
+    teams = 0
+    for t, k in zip(tables, keys):
+        _check_against_oracle(t, k, 256)
+        s = t.summary.cpu().numpy()
+        want = G if t.desc.ncells >= tmin else 1
+        assert int(s[4]) == want
+        teams += want > 1
+    assert teams >= 5
+
+
+@pytest.mark.parametrize("ntables,G", [(1, 64), (3, 16), (2, 2)])
+def test_team_schedule_few_tables(ntables, G):
+    # fewer tables than a team has members: the launch still holds a whole team
+    need_gpu()
+    specs = [((1 << 18) + 17 * i, 3, int(0.7 * 0.818 * ((1 << 18) + 17 * i)), 60 + i)
+             for i in range(ntables)]
+    tables, keys, pristine = _make_tables(specs, 256)
+    ent = pk.batch_entries(tables, "cuda")
+    say("team few tables", ntables, G)
+    pk.iblt_list_batched(ent, ntables, max(x[0] for x in specs), 256, tile_min_cells=1 << 16,
+                         tile_workgroups=G)
+    torch.cuda.synchronize()
+    for t, k in zip(tables, keys):
+        _check_against_oracle(t, k, 256)
+        assert int(t.summary[4].item()) == G
+
+
+def test_team_schedule_limits():
+    # a team table with a round limit, one with a tiny output capacity, one
+    # with a corrupt cell, and one above the threshold (a core is left)
+    need_gpu()
+    N = 1 << 15
+    specs = [(N, 3, int(0.70 * 0.818 * N), 71), (N, 3, int(0.70 * 0.818 * N), 72),
+             (N, 3, int(0.70 * 0.818 * N), 73), (N, 4, int(0.85 * N), 74)]
+    tables, keys, _ = _make_tables(specs, 3)
+    tables[1] = pk.batch_table(tables[1].desc, tables[1].cells, 3, out_cap=1000)
+    o2 = native.iblt_insert(N, 3, gen.table_seed(73), keys[2])
+    c = int(np.flatnonzero(o2.count == 1)[0])
+    tables[2].cells[c, 2] ^= 1 << 40
+    ent = pk.batch_entries(tables, "cuda")
+    say("team limits")
+    pk.iblt_list_batched(ent, len(tables), N, 3, tile_min_cells=N, tile_workgroups=8)
+    torch.cuda.synchronize()
+    for i, (t, k) in enumerate(zip(tables, keys)):
+        if i == 2:
+            # the oracle lists the same corrupted table
+            o2.hash_sum[c] ^= np.uint64(1 << 40)
+            o = native.iblt_list_rounds(o2, max_rounds=3)
+            s, K, groups = _result(t)
+            assert o.corrupt and int(s[3]) & pk.FLAG_ECORRUPT
+            assert np.array_equal(K, o.K)
+            for a, b in zip(groups, o.per_round()):
+                assert np.array_equal(a, b)
+            count, ksum, hsum, ok = table_to_numpy(t.cells)
+            assert np.array_equal(count, o2.count) and np.array_equal(ksum, o2.key_sum)
+            assert np.array_equal(hsum, o2.hash_sum)
+            continue
+        _check_against_oracle(t, k, 3)
+    assert int(tables[0].summary[3].item()) & pk.FLAG_EROUNDS
+    assert int(tables[1].summary[3].item()) & pk.FLAG_ENOSPC
+
+
+def test_team_schedule_graph_replays():
+    # captured once, replayed three times on restored tables: every replay exact
+    need_gpu()
+    specs = _specs(24, 9, lo=10, hi=16, rs=(3,))
+    specs.sort(key=lambda x: -x[0])
+    tables, keys, pristine = _make_tables(specs, 128)
+    ent = pk.batch_entries(tables, "cuda")
+    maxc = max(x[0] for x in specs)
+    ws = pk.workspace(pk.iblt_list_batched_workspace(len(tables), maxc), "cuda")
+    kw = dict(block_threads=512, tile_min_cells=1 << 13, tile_workgroups=8, ws=ws)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pk.iblt_list_batched(ent, len(tables), maxc, 128, **kw)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    for t, p in zip(tables, pristine):
+        t.cells.copy_(p)
+    with torch.cuda.graph(g):
+        pk.iblt_list_batched(ent, len(tables), maxc, 128, **kw)
+    for rep in range(3):
+        for t, p in zip(tables, pristine):
+            t.cells.copy_(p)
+        torch.cuda.synchronize()
+        say("team graph replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        for t, k in zip(tables, keys):
+            _check_against_oracle(t, k, 128)
+
+
+def test_autotuner_per_class_schedule_is_exact():
+    # the tuner times each size class on its own tables, combines the choices
+    # and leaves every table as it found it; its schedule lists exactly
+    need_gpu()
+    from paper_1302_7014_amd.autotune import LARGE_MIN, tune_batched
+    specs = _specs(20, 13, lo=8, hi=12, rs=(3,)) + [
+        (LARGE_MIN + 1000 * i, 3, int(0.7 * 0.818 * LARGE_MIN), 900 + i) for i in range(3)]
+    specs.sort(key=lambda x: -x[0])
+    tables, keys, pristine = _make_tables(specs, 128)
+    ent = pk.batch_entries(tables, "cuda")
+    maxc = max(x[0] for x in specs)
+    ws = pk.workspace(pk.iblt_list_batched_workspace(len(tables), maxc), "cuda")
+    say("autotuner")
+    sched, rep = tune_batched(tables, ent, maxc, 128, ws, reps=1)
+    assert set(rep["classes"]) == {"small", "medium", "large"}
+    assert len(rep["combined"]) == 3
+    for t, p in zip(tables, pristine):
+        assert torch.equal(t.cells, p)
+    pk.iblt_list_batched(ent, len(tables), maxc, 128, ws=ws, **sched)
+    torch.cuda.synchronize()
+    for t, k in zip(tables, keys):
+        _check_against_oracle(t, k, 128)

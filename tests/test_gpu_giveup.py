@@ -63,3 +63,29 @@ def test_list_gives_up_then_next_call_exact(ncells, monkeypatch):
     monkeypatch.delenv("PEEL_BARRIER_TIMEOUT_MS")
     say("after give up: list", ncells)
     check_list(ncells, r, seed, keys)
+
+
+def test_batched_team_gives_up_then_next_call_exact(monkeypatch):
+    # a team's barrier gives up: its tables report PEEL_FLAG_TIMEOUT, every
+    # workgroup leaves, and the next call lists the same tables exactly
+    need_gpu()
+    from test_gpu_batched import _check_against_oracle, _make_tables
+    N = 1 << 16
+    specs = [(N, 3, int(0.7 * 0.818 * N), 80 + i) for i in range(6)]
+    tables, keys, pristine = _make_tables(specs, 64)
+    ent = pk.batch_entries(tables, "cuda")
+    monkeypatch.setenv("PEEL_BARRIER_TIMEOUT_MS", "0")
+    say("give up: batched teams")
+    pk.iblt_list_batched(ent, len(tables), N, 64, tile_min_cells=N, tile_workgroups=16)
+    torch.cuda.synchronize()
+    assert any(int(t.summary[3].item()) & TIMEOUT for t in tables)
+    monkeypatch.delenv("PEEL_BARRIER_TIMEOUT_MS")
+    for t, p in zip(tables, pristine):
+        t.cells.copy_(p)
+    torch.cuda.synchronize()
+    say("after give up: batched teams")
+    pk.iblt_list_batched(ent, len(tables), N, 64, tile_min_cells=N, tile_workgroups=16)
+    torch.cuda.synchronize()
+    for t, k in zip(tables, keys):
+        _check_against_oracle(t, k, 64)
+        assert int(t.summary[3].item()) == 0

@@ -155,6 +155,12 @@ def batched_partial() -> BatchSpec:
                      hot_frac=0.05, hot_lo=1.0, hot_hi=1.2)
 
 
+def batched_few_large() -> BatchSpec:
+    """16 tables of 2^20 cells at 0.7 c*: fewer tables than the GPU has CUs, the
+    case a team of workgroups per table is for."""
+    return BatchSpec("iblt_batched_16x1M_r3", 16, 3, 20.0, 20.0, 0.7, 0.7)
+
+
 @dataclass(frozen=True)
 class ServeSpec:
     """Poisson arrivals of IBLT list requests of mixed sizes (served decoding)."""
