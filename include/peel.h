@@ -281,7 +281,14 @@ peel_status iblt_update(const iblt_desc *desc, iblt_cell *cells, const uint64_t 
  *                if a count-1 cell failed its checksum; such a cell is not
  *                pure), [4] the workgroups that ran the rounds (diagnostic),
  *                [5..7] 0.
- *   ws           (device) ws_bytes >= iblt_list_workspace(desc).
+ *   ws           (device) ws_bytes >= iblt_list_workspace(desc): about
+ *                (16 r + 32) bytes per cell.
+ * The rounds run in one persistent kernel.  Each workgroup owns a range of
+ * cells and is their only writer: a listed key's deletions from its other
+ * cells are sent to those cells' owners, which combine them and update each
+ * cell with one plain read-modify-write (no device atomics).  With
+ * PEEL_LIST_ENGINE=atomic in the environment the deletions are device
+ * atomics instead (the signed listing's engine); the results are the same.
  */
 size_t iblt_list_workspace(const iblt_desc *desc);
 peel_status iblt_list(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys,

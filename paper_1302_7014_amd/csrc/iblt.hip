@@ -22,6 +22,7 @@
 // Round 1's candidates are all cells (one dense pass, which also sums the
 // counts).  Every cell pure at the start of round t+1 went 2 -> 1 during
 // round t, so the candidate lists miss none.
+#include <cstring>
 #include <type_traits>
 
 #include "common.hpp"
@@ -642,6 +643,357 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
     if (!sum_barrier(&ctrl->bar, T, slot, staged, &epoch, a.limit, &total, ctrl->stamp, &prefix))
       return;
     ovf = __hip_atomic_load(&ctrl->ovf_own[npar], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (slot == 0 && tid == 0) {
+    ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
+    ctrl->listed = listed;
+    ctrl->team_size = T;
+  }
+}
+
+// ===========================================================================
+// Owner engine for the plain listing (the default).  Device-scope atomics run
+// at a fixed ~27 G/s on this GPU, and the persistent kernel above spends three
+// per cell a listed key leaves.  Here each of T workgroups owns a range of
+// cr = ceil(N / T) cells and is their only writer:
+//   detect  each owner examines its candidates (round 1: all its cells; then
+//           the cells whose count fell to 1), with the read-only ownership
+//           test of the kernel above, and keeps the keys its cells list; for
+//           each it makes one message (cell, key) per other cell of the key,
+//           to that cell's owner.  The messages are written into the sender's
+//           own region, sorted by destination (kMC at a time ranked and sorted
+//           in LDS, so neighbouring lanes store neighbouring words), and the
+//           per-destination counts and starts are published.
+//   apply   after the barrier, each owner reads the runs addressed to it from
+//           every sender, combines the updates of each cell in an LDS hash
+//           table (kAC at a time: count, key XOR, checksum XOR), and applies
+//           each with one plain 32-byte read-modify-write; a cell whose count
+//           becomes 1 is its own next candidate.  It clears the cells its keys
+//           were listed from and writes its keys to out.
+// Two barriers a round, as above; no device atomic per key or per cell.  Every
+// list has a fixed bound: an owner lists at most one key per cell it owns and
+// pushes each of its cells at most once a round, and sends at most r - 1
+// messages per key it lists.
+constexpr uint32_t kLMaxT = 1024;   // owners (LDS per-destination counters)
+constexpr uint32_t kMC = 2048;      // messages sorted in LDS at a time
+constexpr uint32_t kOAC = 2048;     // messages combined in LDS at a time
+constexpr uint32_t kOHBits = 12;
+constexpr uint32_t kOHS = 1u << kOHBits;  // hash slots for one apply chunk
+static_assert(2 * kOAC <= kOHS, "the apply's hash table stays at most half full");
+
+struct OwnArgs {
+  Hash h;
+  iblt_cell *cells;
+  uint64_t *out;
+  uint64_t out_cap;
+  uint64_t *stats;
+  uint64_t *keys;   // N: the keys each owner lists this round (at its first cell)
+  uint32_t *ownc;   // N: the cells they were listed from
+  uint32_t *cand;   // N: each owner's candidates for the next round
+  uint4 *msg;       // (r-1) N: each owner's outgoing messages {cell, 0, key lo, key hi}
+  uint32_t *mcnt;   // grid x grid: messages from owner s to owner d at [s * grid + d]
+  uint32_t *moff;   // grid x grid: where in s's region they start
+  ListCtrl *ctrl;
+  uint64_t limit;
+  uint64_t quiet;
+  uint64_t team_limit;
+  uint32_t ncells;
+  uint32_t max_rounds;
+  uint32_t grid;
+};
+
+struct OwnSlot {  // LDS: one cell's combined updates in an apply chunk
+  unsigned long long ks;
+  unsigned long long hs;
+  uint32_t cell;
+  int32_t n;
+};
+
+template <int R>
+__global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
+  // keys whose messages are sorted at a time: one per thread, at most kMC messages
+  constexpr uint32_t kKC = kMC / (R - 1) < (uint32_t)kLT ? kMC / (R - 1) : (uint32_t)kLT;
+  // the send's sort buffer and the apply's hash table share one LDS area
+  constexpr size_t kPool = kOHS * sizeof(OwnSlot) > kMC * sizeof(uint4) + kMC * 2
+                               ? kOHS * sizeof(OwnSlot) : kMC * sizeof(uint4) + kMC * 2;
+  __shared__ __align__(16) unsigned char pool[kPool];
+  __shared__ uint32_t cnt[kLMaxT];
+  __shared__ uint32_t cur[kLMaxT];
+  __shared__ uint32_t sst[kLMaxT];
+  __shared__ uint32_t inpre[kLMaxT + 1];
+  __shared__ uint32_t scan_lds[kLT / kWave + 1];
+  __shared__ uint32_t s_own, s_cand, s_bad;
+  __shared__ unsigned long long s_sum;
+
+  ListCtrl *ctrl = a.ctrl;
+  uint32_t slot, T;
+  if (!team_join(&ctrl->team, a.quiet, a.team_limit, &slot, &T)) return;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t N = a.ncells;
+  if (T > kLMaxT) {  // cannot happen: the grid is at most the CU count
+    if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_TIMEOUT);
+    return;
+  }
+  const uint32_t cr = (N + T - 1) / T;
+  const uint32_t c0 = slot * cr < N ? slot * cr : N;
+  const uint32_t c1 = c0 + cr < N ? c0 + cr : N;
+  uint64_t *myKeys = a.keys + c0;
+  uint32_t *myOwn = a.ownc + c0;
+  uint32_t *myCand = a.cand + c0;
+  uint4 *myMsg = a.msg + (uint64_t)(R - 1) * c0;
+  uint4 *sbuf = reinterpret_cast<uint4 *>(pool);
+  uint16_t *sdst = reinterpret_cast<uint16_t *>(pool + kMC * sizeof(uint4));
+  OwnSlot *hslot = reinterpret_cast<OwnSlot *>(pool);
+  const Hash &h = a.h;
+
+  if (tid == 0) {
+    s_own = 0;
+    s_bad = 0;
+    s_sum = 0;
+  }
+  if (slot == 0)
+    for (uint32_t i = tid; i < a.max_rounds; i += kLT) a.stats[i] = 0;
+  __syncthreads();
+  auto take = [&](uint64_t ks, uint32_t c) {
+    const uint32_t pos = atomicAdd(&s_own, 1u);
+    myKeys[pos] = ks;
+    myOwn[pos] = c;
+  };
+  // ---- round-1 detect over my cells ------------------------------------------
+  {
+    long long local = 0;
+    uint32_t bad = 0;
+    detect_cells<R, false>(
+        h, a.cells, c0, c1, tid, kLT, [](uint64_t i) { return static_cast<uint32_t>(i); }, take,
+        &bad, &local);
+    if (bad) s_bad = 1;
+    atomicAdd(&s_sum, (unsigned long long)local);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (s_sum) atomicAdd(&ctrl->count_sum, s_sum);
+    if (s_bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
+  }
+
+  // the keys of round t leave their other cells: messages to those cells' owners
+  auto send = [&](uint32_t nk) {
+    for (uint32_t d = tid; d < T; d += kLT) cnt[d] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < nk; i += kLT) {
+      const uint64_t x = myKeys[i];
+      const uint32_t jo = subtable_of(h, myOwn[i]);
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if ((uint32_t)j != jo) atomicAdd(&cnt[cell_of(h, j, x) / cr], 1u);
+    }
+    __syncthreads();
+    uint32_t base = 0;
+    for (uint32_t d0 = 0; d0 < T; d0 += kLT) {
+      const uint32_t d = d0 + tid;
+      uint32_t tot;
+      const uint32_t ex = block_exclusive_scan<kLT>(d < T ? cnt[d] : 0u, &tot, scan_lds);
+      if (d < T) {
+        cur[d] = base + ex;
+        a.mcnt[(uint64_t)slot * a.grid + d] = cnt[d];
+        a.moff[(uint64_t)slot * a.grid + d] = base + ex;
+      }
+      base += tot;
+    }
+    __syncthreads();
+    for (uint32_t k0 = 0; k0 < nk; k0 += kKC) {
+      for (uint32_t d = tid; d < T; d += kLT) cnt[d] = 0;
+      __syncthreads();
+      const uint32_t i = k0 + tid;
+      uint64_t x = 0;
+      uint32_t cl[R], rk[R];
+      bool live = tid < kKC && i < nk;
+      uint32_t jo = R;
+      if (live) {
+        x = myKeys[i];
+        jo = subtable_of(h, myOwn[i]);
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        cl[j] = cell_of(h, j, x);
+        if (live && (uint32_t)j != jo) rk[j] = atomicAdd(&cnt[cl[j] / cr], 1u);
+      }
+      __syncthreads();
+      uint32_t tot = 0, run = 0;
+      for (uint32_t d0 = 0; d0 < T; d0 += kLT) {
+        const uint32_t d = d0 + tid;
+        uint32_t t0;
+        const uint32_t ex = block_exclusive_scan<kLT>(d < T ? cnt[d] : 0u, &t0, scan_lds);
+        if (d < T) sst[d] = run + ex;
+        run += t0;
+      }
+      tot = run;
+      __syncthreads();
+      if (live) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if ((uint32_t)j == jo) continue;
+          const uint32_t d = cl[j] / cr;
+          const uint32_t p = sst[d] + rk[j];
+          sbuf[p] = make_uint4(cl[j], 0u, static_cast<uint32_t>(x), static_cast<uint32_t>(x >> 32));
+          sdst[p] = static_cast<uint16_t>(d);
+        }
+      }
+      __syncthreads();
+      for (uint32_t q = tid; q < tot; q += kLT) {
+        const uint32_t d = sdst[q];
+        myMsg[cur[d] + (q - sst[d])] = sbuf[q];
+      }
+      __syncthreads();
+      for (uint32_t d = tid; d < T; d += kLT) cur[d] += cnt[d];
+    }
+  };
+
+  uint32_t nk = s_own;
+  send(nk);
+  uint32_t epoch = 0;
+  uint64_t total, prefix;
+  if (!sum_barrier(&ctrl->bar, T, slot, nk, &epoch, a.limit, &total, ctrl->stamp, &prefix)) return;
+
+  uint64_t listed = 0;
+  uint32_t t = 1;
+  for (;; ++t) {
+    const uint64_t K = total;
+    if (K == 0) break;
+    if (t > a.max_rounds || listed + K > a.out_cap) {
+      if (slot == 0 && tid == 0)
+        atomicOr(&ctrl->flags, t > a.max_rounds ? PEEL_FLAG_EROUNDS : PEEL_FLAG_ENOSPC);
+      break;
+    }
+    if (slot == 0 && tid == 0) a.stats[t - 1] = K;
+    // ---- apply ---------------------------------------------------------------
+    for (uint32_t i = tid; i < nk; i += kLT) {
+      a.out[listed + prefix + i] = myKeys[i];
+      clear_cell(a.cells + myOwn[i]);
+    }
+    // the runs addressed to me, one per sender, laid end to end
+    uint32_t nin = 0;
+    for (uint32_t s0 = 0; s0 < T; s0 += kLT) {
+      const uint32_t sd = s0 + tid;
+      uint32_t tot;
+      const uint32_t x = sd < T ? a.mcnt[(uint64_t)sd * a.grid + slot] : 0u;
+      const uint32_t ex = block_exclusive_scan<kLT>(x, &tot, scan_lds);
+      if (sd < T) {
+        inpre[sd] = nin + ex;
+        sst[sd] = a.moff[(uint64_t)sd * a.grid + slot];
+      }
+      nin += tot;
+    }
+    if (tid == 0) {
+      inpre[T] = nin;
+      s_cand = 0;
+    }
+    __syncthreads();
+    // kOAC messages a chunk, kOU per thread.  A chunk's messages were loaded
+    // during the previous chunk, and each thread loads the cells of its
+    // messages before the hashing, so that one global latency per chunk is
+    // exposed; the cell a leader loaded is current, since only the leader of a
+    // cell writes it in a chunk and the chunk before has finished.
+    constexpr int kOU = (int)(kOAC / kLT);
+    auto fetch = [&](uint32_t m0, uint4 *mm) {
+#pragma unroll
+      for (int u = 0; u < kOU; ++u) {
+        const uint32_t i = m0 + (uint32_t)u * kLT + tid;
+        mm[u] = make_uint4(0xffffffffu, 0u, 0u, 0u);
+        if (i >= nin) continue;
+        // the sender whose run holds incoming message i
+        uint32_t lo = 0, hi = T;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (inpre[mid] <= i) lo = mid; else hi = mid;
+        }
+        mm[u] = a.msg[(uint64_t)(R - 1) * (lo * cr) + sst[lo] + (i - inpre[lo])];
+      }
+    };
+    uint4 mnext[kOU];
+    fetch(0, mnext);
+    for (uint32_t m0 = 0; m0 < nin; m0 += kOAC) {
+      uint4 mm[kOU], x0[kOU];
+      uint2 x1[kOU];  // the hash sum; the cell's last 8 bytes are not touched
+#pragma unroll
+      for (int u = 0; u < kOU; ++u) {
+        mm[u] = mnext[u];
+        if (mm[u].x != 0xffffffffu) {
+          const uint4 *p = reinterpret_cast<const uint4 *>(a.cells + mm[u].x);
+          x0[u] = p[0];
+          x1[u] = *reinterpret_cast<const uint2 *>(p + 1);
+        }
+      }
+      for (uint32_t q = tid; q < kOHS; q += kLT) {
+        hslot[q].cell = 0xffffffffu;
+        hslot[q].n = 0;
+        hslot[q].ks = 0ull;
+        hslot[q].hs = 0ull;
+      }
+      __syncthreads();
+      uint32_t lead[kOU];
+#pragma unroll
+      for (int u = 0; u < kOU; ++u) {
+        lead[u] = 0xffffffffu;
+        const uint32_t c = mm[u].x;
+        if (c == 0xffffffffu) continue;
+        const uint64_t x = (uint64_t)mm[u].z | ((uint64_t)mm[u].w << 32);
+        uint32_t q = (c * 0x9e3779b1u) >> (32 - kOHBits);
+        for (;;) {
+          const uint32_t old = atomicCAS(&hslot[q].cell, 0xffffffffu, c);
+          if (old == 0xffffffffu) {
+            lead[u] = q;
+            break;
+          }
+          if (old == c) break;
+          q = (q + 1) & (kOHS - 1);
+        }
+        atomicAdd(&hslot[q].n, 1);
+        atomicXor(&hslot[q].ks, (unsigned long long)x);
+        atomicXor(&hslot[q].hs, (unsigned long long)check_of(h, x));
+      }
+      fetch(m0 + kOAC, mnext);  // in flight while the chunk is applied
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kOU; ++u) {
+        if (lead[u] == 0xffffffffu) continue;
+        const OwnSlot &sl = hslot[lead[u]];
+        const int32_t now = static_cast<int32_t>(x0[u].x) - sl.n;
+        x0[u].x = static_cast<uint32_t>(now);
+        x0[u].z ^= static_cast<uint32_t>(sl.ks);
+        x0[u].w ^= static_cast<uint32_t>(sl.ks >> 32);
+        x1[u].x ^= static_cast<uint32_t>(sl.hs);
+        x1[u].y ^= static_cast<uint32_t>(sl.hs >> 32);
+        uint4 *p = reinterpret_cast<uint4 *>(a.cells + sl.cell);
+        p[0] = x0[u];
+        *reinterpret_cast<uint2 *>(p + 1) = x1[u];
+        if (now == 1) myCand[atomicAdd(&s_cand, 1u)] = sl.cell;
+      }
+      __syncthreads();
+    }
+    listed += K;
+    uint64_t dummy;
+    if (!sum_barrier(&ctrl->bar, T, slot, 0, &epoch, a.limit, &dummy, ctrl->stamp)) return;
+    // ---- detect for round t+1 over my candidates ------------------------------
+    const uint32_t ncand = s_cand;
+    if (tid == 0) {
+      s_own = 0;
+      s_bad = 0;
+    }
+    __syncthreads();
+    {
+      uint32_t bad = 0;
+      long long unused = 0;
+      detect_cells<R, false>(
+          h, a.cells, 0, ncand, tid, kLT, [&](uint64_t i) { return myCand[i]; }, take, &bad,
+          &unused);
+      if (bad) s_bad = 1;
+    }
+    __syncthreads();
+    if (tid == 0 && s_bad) atomicOr(&ctrl->flags, PEEL_FLAG_ECORRUPT);
+    nk = s_own;
+    send(nk);
+    if (!sum_barrier(&ctrl->bar, T, slot, nk, &epoch, a.limit, &total, ctrl->stamp, &prefix))
+      return;
   }
   if (slot == 0 && tid == 0) {
     ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
@@ -1723,9 +2075,20 @@ bool list_first_binned_fits(const iblt_desc *d) {
   return d->workgroups == 0 && d->ncells >= kListBinnedMin && upd_binned(d, d->ncells);
 }
 
+// The owner engine's arrays: keys, their cells and the candidates (one entry
+// per cell), (r-1) 16-byte messages per cell, and the owners' message tables.
+size_t owner_ws_bytes(const iblt_desc *d) {
+  const ListLayout L = list_layout(d->ncells, d->workgroups);
+  const uint64_t N = d->ncells, g = L.grid;
+  return L.ctrl + align_up(N * 8) + 2 * align_up(N * 4) + align_up((uint64_t)(d->r - 1) * N * 16) +
+         2 * align_up(g * g * 4);
+}
+
 size_t list_ws_bytes(const iblt_desc *d) {
   const ListLayout L = list_layout(d->ncells, d->workgroups);
   size_t need = L.total;
+  const size_t o = owner_ws_bytes(d);
+  need = o > need ? o : need;
   if (list_first_binned_fits(d)) {
     const size_t b = L.ctrl + upd_ws_bytes(d, d->ncells);
     need = b > need ? b : need;
@@ -1802,6 +2165,55 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
   hipLaunchKernelGGL(k_list_init, dim3(1), dim3(256), 0, s, a.ctrl);
   PEEL_HIP_TRY(hipGetLastError());
   peel_status st;
+  // The plain listing runs on the owner engine; PEEL_LIST_ENGINE=atomic (or a
+  // PEEL_LIST_SLOT_CAP, which exercises the atomic kernel's overflow queues)
+  // selects the persistent kernel with device-atomic deletes instead.
+  const char *eng = std::getenv("PEEL_LIST_ENGINE");
+  const bool atomic_engine = (eng && std::strcmp(eng, "atomic") == 0) || slot_cap > 0;
+  if (!subtables && !signed_list && !atomic_engine) {
+    if (ws_bytes < owner_ws_bytes(desc)) return PEEL_ENOSPC;
+    OwnArgs o{};
+    o.h = a.h;
+    o.cells = cells;
+    o.out = out_keys;
+    o.out_cap = out_cap;
+    o.stats = round_stats;
+    o.ctrl = a.ctrl;
+    o.limit = a.limit;
+    o.quiet = a.quiet;
+    o.team_limit = a.team_limit;
+    o.ncells = a.ncells;
+    o.max_rounds = max_rounds;
+    o.grid = L.grid;
+    const uint64_t N = desc->ncells, g = L.grid;
+    char *ob = static_cast<char *>(ws) + L.ctrl;
+    o.keys = reinterpret_cast<uint64_t *>(ob);
+    ob += align_up(N * 8);
+    o.ownc = reinterpret_cast<uint32_t *>(ob);
+    ob += align_up(N * 4);
+    o.cand = reinterpret_cast<uint32_t *>(ob);
+    ob += align_up(N * 4);
+    o.msg = reinterpret_cast<uint4 *>(ob);
+    ob += align_up((uint64_t)(desc->r - 1) * N * 16);
+    o.mcnt = reinterpret_cast<uint32_t *>(ob);
+    ob += align_up(g * g * 4);
+    o.moff = reinterpret_cast<uint32_t *>(ob);
+    if (device_info().debug) std::fprintf(stderr, "[peel] list owner grid %u\n", o.grid);
+    switch (desc->r) {
+      case 2: hipLaunchKernelGGL(k_list_owner<2>, dim3(o.grid), dim3(kLT), 0, s, o); break;
+      case 3: hipLaunchKernelGGL(k_list_owner<3>, dim3(o.grid), dim3(kLT), 0, s, o); break;
+      case 4: hipLaunchKernelGGL(k_list_owner<4>, dim3(o.grid), dim3(kLT), 0, s, o); break;
+      case 5: hipLaunchKernelGGL(k_list_owner<5>, dim3(o.grid), dim3(kLT), 0, s, o); break;
+      case 6: hipLaunchKernelGGL(k_list_owner<6>, dim3(o.grid), dim3(kLT), 0, s, o); break;
+      case 7: hipLaunchKernelGGL(k_list_owner<7>, dim3(o.grid), dim3(kLT), 0, s, o); break;
+      default: hipLaunchKernelGGL(k_list_owner<8>, dim3(o.grid), dim3(kLT), 0, s, o); break;
+    }
+    PEEL_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_list_finish, dim3(1), dim3(64), 0, s, a.ctrl, desc->r, summary, 0u,
+                       round_stats, 0u);
+    PEEL_HIP_TRY(hipGetLastError());
+    return PEEL_OK;
+  }
   // Round 1 binned: a plain listing with room for every key (so round 1 always
   // runs, as in the persistent kernel) and at least two rounds allowed; the
   // persistent kernel then runs rounds 2, 3, ... with one round fewer allowed.

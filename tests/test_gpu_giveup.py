@@ -44,10 +44,14 @@ def test_peel_gives_up_then_next_call_exact(engine, subtables, monkeypatch):
     assert np.array_equal(res["deg"], o.deg)
 
 
+@pytest.mark.parametrize("engine", ["owner", "atomic"])
 @pytest.mark.parametrize("ncells", [1 << 14, (1 << 20) + 77])
-def test_list_gives_up_then_next_call_exact(ncells, monkeypatch):
-    # 2^20 + 77 cells also takes the binned first round before the persistent kernel
+def test_list_gives_up_then_next_call_exact(ncells, engine, monkeypatch):
+    # with the atomic engine, 2^20 + 77 cells also takes the binned first round
+    # before the persistent kernel
     need_gpu()
+    if engine == "atomic":
+        monkeypatch.setenv("PEEL_LIST_ENGINE", "atomic")
     r, seed = 3, 43
     keys = gen.distinct_keys(int(0.7 * ncells), seed)
     d, cells = gpu_insert(ncells, r, seed, keys)

@@ -17,6 +17,18 @@ from gpu_helpers import dev_u64, host_u64, need_gpu, say, table_to_numpy
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True, params=["owner", "atomic"])
+def list_engine(request, monkeypatch):
+    """Every listing test runs on both engines: the owner engine (the default:
+    each workgroup owns a range of cells and applies their updates with plain
+    read-modify-writes) and the persistent kernel with device-atomic deletes."""
+    if request.param == "atomic":
+        monkeypatch.setenv("PEEL_LIST_ENGINE", "atomic")
+    else:
+        monkeypatch.delenv("PEEL_LIST_ENGINE", raising=False)
+    return request.param
+
+
 def gpu_insert(ncells, r, seed, keys):
     d = pk.iblt_desc(ncells, r, seed)
     cells = pk.iblt_table(ncells, "cuda")

@@ -15,6 +15,12 @@ from gpu_helpers import dev_u64, host_u64, need_gpu, say, table_to_numpy
 
 pytestmark = pytest.mark.gpu
 
+
+@pytest.fixture(autouse=True)
+def atomic_engine(monkeypatch):
+    """The binned first round belongs to the device-atomic listing engine."""
+    monkeypatch.setenv("PEEL_LIST_ENGINE", "atomic")
+
 N = (1 << 20) + 77
 
 
