@@ -313,8 +313,9 @@ def _tuner_summary(rep):
     return out
 
 
-def bench_batched(spec, reps):
-    """One launch for every table (block-per-table schedule) vs one iblt_list per table."""
+def bench_batched(spec, reps, sched=None):
+    """One launch for every table (schedule tuned per size class, or `sched`) vs
+    one iblt_list per table."""
     draw = spec.draw(1)
     order = sorted(range(len(draw)), key=lambda i: -draw[i][0])
     dev = torch.device("cuda", 0)
@@ -339,8 +340,10 @@ def bench_batched(spec, reps):
         torch.cuda.synchronize()
 
     # pick the schedule on this batch, then capture the batched call in a graph
-    from paper_1302_7014_amd.autotune import tune_batched
-    sched, tuner = tune_batched(tables, ent, maxc, 256, ws)
+    tuner = None
+    if sched is None:
+        from paper_1302_7014_amd.autotune import tune_batched
+        sched, tuner = tune_batched(tables, ent, maxc, 256, ws)
     log(f"batched schedule {sched}")
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -374,7 +377,7 @@ def bench_batched(spec, reps):
     return {
         "workload": spec.name, "tables": len(tables), "cells": int(sum(x[0] for x in draw)),
         "keys": nkeys, "listed": listed, "incomplete_tables": incomplete,
-        "schedule": sched, "tuner": _tuner_summary(tuner),
+        "schedule": sched, "tuner": _tuner_summary(tuner) if tuner else None,
         "batched_graph_ms": bt, "plain_per_table_ms": pt, "speedup": pt / bt,
         "batched_keys_per_s": listed / (bt * 1e-3), "plain_keys_per_s": listed_plain / (pt * 1e-3),
         # the listing's algorithmic bytes summed over the tables (each table's
@@ -544,6 +547,12 @@ def main():
                          "workload alone)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-xor", action="store_true", help="skip the CSR-free k = 2 peel")
+    ap.add_argument("--batched-main-only", action="store_true",
+                    help="of the batched workloads, only the 4096-table batch")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched listing with the schedule the tuner picks for the 4096-table "
+                         "batch (1024 threads, LDS tables up to 2048 cells), no tuning runs "
+                         "(profiles of one schedule)")
     ap.add_argument("--iblt-main", action="store_true",
                     help="of the IBLT workloads, only the 2^24-cell main one (profiles of one shape)")
     ap.add_argument("--no-serve", action="store_true")
@@ -612,11 +621,17 @@ def main():
         extra["k3"] = k3
     if not args.no_batched:
         log("batched IBLT listing (4096 tables)")
-        extra["batched"] = bench_batched(configs.batched_main(), 3)
-        log("batched IBLT listing, 5% of the tables above threshold")
-        extra["batched_partial"] = bench_batched(configs.batched_partial(), 3)
-        log("batched IBLT listing, 16 tables of 2^20 cells")
-        extra["batched_few_large"] = bench_batched(configs.batched_few_large(), 3)
+        fixed = ({"block_threads": 1024, "lds_max_cells": pk.IBLT_LDS_MAX_CELLS,
+                  "tile_min_cells": 0, "tile_workgroups": 0} if args.no_tune else None)
+        extra["batched"] = bench_batched(configs.batched_main(), 3, fixed)
+        if not args.batched_main_only:
+            log("batched IBLT listing, 5% of the tables above threshold")
+            extra["batched_partial"] = bench_batched(configs.batched_partial(), 3, fixed)
+            log("batched IBLT listing, 16 tables of 2^20 cells")
+            extra["batched_few_large"] = bench_batched(
+                configs.batched_few_large(), 3,
+                {**fixed, "lds_max_cells": 0, "tile_min_cells": 1 << 17, "tile_workgroups": 16}
+                if fixed else None)
     if not args.no_iblt:
         log("IBLT 2^24 cells")
         extra["iblt"] = [bench_iblt(configs.iblt_main(), 5)]

@@ -224,6 +224,12 @@ typedef struct iblt_desc {
  * the caller zeroes before the first insert.  Keys (device) must be
  * distinct from each other and from keys already in the table: a repeated
  * key cancels in the XOR fields.
+ *
+ * Each key costs 3 r device atomics, which run at a fixed rate on this GPU
+ * (about 27 G/s, about 370 GB/s of cell traffic): this is the call for small
+ * tables and for callers without a workspace.  For a table larger than the
+ * caches, iblt_update (below) gives the same cells bit for bit, 4-5 times
+ * faster (2^24 cells, 10.3 M keys: 0.78 ms against 3.56 ms).
  */
 peel_status iblt_insert(const iblt_desc *desc, iblt_cell *cells, const uint64_t *keys,
                         uint64_t nkeys, void *stream);
