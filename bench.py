@@ -404,11 +404,11 @@ def bench_serve(spec, n_cal, n_rate, warm):
     # Each server first runs `warm` requests unmeasured: the first closed loop
     # pays one-time costs (first touch of the arena, first launches) that made
     # the saturated rate swing by a factor of two with what ran before it.
-    cont = ContinuousServer(spec.budget_bytes, fill, max_cells=1 << 22)
+    cont = ContinuousServer(spec.budget_bytes, fill, max_cells=1 << 22, max_r=max(spec.r_choices))
     cont.run(reqs(warm, 0.0, 4))
     cal = latency_stats(cont.run(reqs(n_cal, 0.0, 5)))
     lam = cal["req_per_s"]
-    fifo = FifoServer(spec.budget_bytes, fill)
+    fifo = FifoServer(spec.budget_bytes, fill, max_r=max(spec.r_choices))
     fifo.run(reqs(warm, 0.0, 4))
     fifo_sat = latency_stats(fifo.run(reqs(n_cal, 0.0, 5)))["req_per_s"]
     out = {"workload": spec.name, "budget_gb": spec.budget_bytes / 2 ** 30,

@@ -208,9 +208,10 @@ typedef struct iblt_cell {
 typedef struct iblt_desc {
     uint64_t ncells;     /* r <= ncells < 2^32 */
     uint32_t r;          /* 2..8 */
-    uint32_t workgroups; /* iblt_list only: persistent workgroups, 0 = one per CU
-                            (more than one per CU is taken as one per CU); callers
-                            that run several listings at once give each a share */
+    uint32_t workgroups; /* iblt_list only: persistent workgroups; 0 = one per
+                            4096 cells, at most one per CU (more than one per CU
+                            is taken as one per CU); callers that run several
+                            listings at once give each a share */
     uint64_t seed;
 } iblt_desc;
 

@@ -1866,10 +1866,18 @@ struct ListLayout {
 };
 
 // grid: the persistent workgroups asked for (0 = one per CU; at most one per CU).
+// Cells per persistent workgroup that a listing's default team aims at: a
+// smaller table is listed by fewer workgroups (measured on 2^10 .. 2^24 cells,
+// this is within a few percent of the best team size at every size, and the
+// whole GPU from 2^20 cells).
+constexpr uint64_t kListCellsPerWG = 4096;
+
 ListLayout list_layout(uint64_t ncells, uint32_t want) {
   ListLayout L{};
   const uint32_t cus = static_cast<uint32_t>(device_info().cus);  // 1024-thread workgroups
-  L.grid = (want == 0 || want > cus) ? cus : want;
+  const uint64_t by_size = (ncells + kListCellsPerWG - 1) / kListCellsPerWG;
+  const uint32_t dflt = by_size < cus ? (by_size ? static_cast<uint32_t>(by_size) : 1u) : cus;
+  L.grid = want == 0 ? dflt : (want > cus ? cus : want);
   L.cb = static_cast<uint32_t>((ncells + L.grid - 1) / L.grid + 4096);
   const uint64_t slots = (uint64_t)L.grid * L.cb;
   L.ctrl = align_up(sizeof(ListCtrl));

@@ -187,7 +187,7 @@ class ContinuousServer(_Base):
     def __init__(self, budget: int, fill_keys, max_cells: int, max_rounds: int = 256,
                  max_inflight: int = 2, block_threads: int = 512, small_cells: int = 1 << 12,
                  large_lanes: int = 4, admit_group: int = 8, keep_keys: bool = False,
-                 device="cuda"):
+                 device="cuda", max_r: int = 8):
         super().__init__(budget, fill_keys, max_rounds, keep_keys, device)
         self.max_cells = max_cells
         self.max_inflight = max_inflight
@@ -202,8 +202,9 @@ class ContinuousServer(_Base):
         cus = torch.cuda.get_device_properties(self.device).multi_processor_count
         self.lane_workgroups = max(1, cus // large_lanes)
         self.large_streams = [torch.cuda.Stream(device=self.device) for _ in range(large_lanes)]
+        # (the listing's workspace grows with r: sized for the largest r served)
         self.large_ws = [pk.workspace(pk.iblt_list_workspace(
-            pk.iblt_desc(max_cells, 3, 0, self.lane_workgroups)), self.device)
+            pk.iblt_desc(max_cells, max_r, 0, self.lane_workgroups)), self.device)
             for _ in range(large_lanes)]
         # one batched-listing workspace per in-flight launch, sized for the largest small table
         self.ws = [pk.workspace(pk.iblt_list_batched_workspace(1 << 16, min(small_cells, max_cells)),
@@ -311,10 +312,11 @@ class FifoServer(_Base):
     """Plain baseline: one request at a time, insert then iblt_list, one stream."""
 
     def __init__(self, budget: int, fill_keys, max_rounds: int = 256, keep_keys: bool = False,
-                 device="cuda", max_cells: int = 1 << 22):
+                 device="cuda", max_cells: int = 1 << 22, max_r: int = 8):
         super().__init__(budget, fill_keys, max_rounds, keep_keys, device)
         self.stream = torch.cuda.Stream(device=self.device)
-        self.ws = pk.workspace(pk.iblt_list_workspace(pk.iblt_desc(max_cells, 3, 0)), self.device)
+        self.ws = pk.workspace(pk.iblt_list_workspace(pk.iblt_desc(max_cells, max_r, 0)),
+                               self.device)
 
     def run(self, requests: list[Request], poll_s: float = 2e-5) -> list[Request]:
         pending = sorted(requests, key=lambda q: q.arrival)

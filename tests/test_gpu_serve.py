@@ -99,3 +99,22 @@ def test_mix_with_large_tables_equals_alone_and_oracle():
         assert int(q.summary[0]) == o.keys.size and int(q.summary[1]) == o.rounds
         assert all(np.array_equal(x, y) for x, y in zip(gm, o.per_round()))
     say("serve mix, large tables: all equal")
+
+
+@pytest.mark.parametrize("r", [3, 4, 8])
+def test_largest_table_of_every_r_is_served(r):
+    # a table of max_cells cells with the largest r the server is sized for
+    # goes through a large lane (whose listing workspace grows with r)
+    need_gpu()
+    n = 1 << 20
+    from oracle import theory
+    m = int(0.6 * theory.cstar(2, r)[0] * n)
+    q = Request(0, 0.0, r, n, m, 7000 + r, gen.table_seed(7000 + r))
+    say("serve largest table, r", r)
+    srv = ContinuousServer(256 << 20, _fill, max_cells=n, keep_keys=True, max_r=8)
+    done = srv.run([q])
+    assert len(done) == 1 and srv.large == 1
+    k = gen.distinct_keys(m, q.key_seed)
+    o = native.iblt_list_rounds(native.iblt_insert(n, r, q.table_seed, k), max_rounds=256)
+    assert int(done[0].summary[0]) == o.keys.size and int(done[0].summary[1]) == o.rounds
+    assert all(np.array_equal(x, y) for x, y in zip(_groups(done[0]), o.per_round()))
