@@ -1375,17 +1375,15 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
   {
     long long local = 0;
     uint32_t bad = 0;
-    for (uint32_t c = tid; c < N; c += NT) {
-      int32_t cnt;
-      uint64_t ks, hs;
-      load_cell(cells + c, &cnt, &ks, &hs);
-      local += cnt;
-      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) {
-        const uint32_t pos = atomicAdd(&s_k, 1u);
-        if (pos < N) own[pos] = c;
-        if (listed + pos < out_cap) out[listed + pos] = ks;
-      }
-    }
+    // kDetU cells per lane in flight (detect_cells)
+    detect_cells<R, false>(
+        h, cells, 0, N, tid, NT, [](uint64_t i) { return static_cast<uint32_t>(i); },
+        [&](uint64_t ks, uint32_t c) {
+          const uint32_t pos = atomicAdd(&s_k, 1u);
+          if (pos < N) own[pos] = c;
+          if (listed + pos < out_cap) out[listed + pos] = ks;
+        },
+        &bad, &local);
     if (bad) s_bad = 1;
     atomicAdd(&s_sum, (unsigned long long)local);
   }
@@ -1415,17 +1413,15 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
     if (tid == 0) s_k = 0;
     __syncthreads();
     uint32_t bad = 0;
-    for (uint32_t i = tid; i < nc; i += NT) {
-      const uint32_t c = cand[i];
-      int32_t cnt;
-      uint64_t ks, hs;
-      load_cell(cells + c, &cnt, &ks, &hs);
-      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) {
-        const uint32_t pos = atomicAdd(&s_k, 1u);
-        own[pos] = c;
-        if (listed + pos < out_cap) out[listed + pos] = ks;
-      }
-    }
+    long long unused = 0;
+    detect_cells<R, false>(
+        h, cells, 0, nc, tid, NT, [&](uint64_t i) { return cand[i]; },
+        [&](uint64_t ks, uint32_t c) {
+          const uint32_t pos = atomicAdd(&s_k, 1u);
+          own[pos] = c;
+          if (listed + pos < out_cap) out[listed + pos] = ks;
+        },
+        &bad, &unused);
     if (bad) s_bad = 1;
     __syncthreads();
   }
