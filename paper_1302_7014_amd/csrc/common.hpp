@@ -83,14 +83,12 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total, uin
   uint32_t inc = wave_inclusive_scan(v);
   if (lane == kWave - 1) lds[wave] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int w = 0; w < NT / kWave; ++w) {
-      uint32_t t = lds[w];
-      lds[w] = acc;
-      acc += t;
-    }
-    lds[NT / kWave] = acc;
+  if (threadIdx.x < kWave) {  // the first wave scans the waves' sums
+    constexpr uint32_t kW = NT / kWave;
+    const uint32_t x = lane < kW ? lds[lane] : 0u;
+    const uint32_t y = wave_inclusive_scan(x);
+    if (lane < kW) lds[lane] = y - x;
+    if (lane == kW - 1) lds[kW] = y;
   }
   __syncthreads();
   uint32_t out = lds[wave] + inc - v;

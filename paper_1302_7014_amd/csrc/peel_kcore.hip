@@ -60,14 +60,30 @@ constexpr int kDenseTile = kBlock * kDenseItems;
 
 constexpr int kOT = 1024;             // threads per owner workgroup
 constexpr uint32_t kOwnMaxV = 98304;  // owned vertices (LDS degree nibbles)
+constexpr uint32_t kOwnMaxVX = 65536; // owned vertices when their dead-edge nibbles fit in LDS too
 constexpr uint32_t kOwnMaxE = 65536;  // owned edges (LDS alive and claimed bits)
-constexpr uint32_t kOwnMaxT = 1024;   // owner workgroups (LDS per-destination counters)
+constexpr uint32_t kOwnMaxT = 256;    // owner workgroups (LDS per-destination counters)
 constexpr uint64_t kDenseRatio = 3;   // dense round when |F_{t-1}| * 3 >= alive edges
 constexpr uint32_t kNoVertex = 0xffffffffu;
 constexpr uint32_t kNib = 15;         // escape value of the owner engine's 4-bit fields
 constexpr int kSendU = 4;             // messages per thread in one sorted send chunk
 constexpr uint32_t kSendChunk = kSendU * kOT;  // messages sorted in LDS at a time
 constexpr int kLU = 4;                // queue entries per thread whose loads are in flight
+constexpr int kCV = 2;                // frontier vertices per lane in one pass of the claim walk
+constexpr int kCE = 8;                // incidences per frontier vertex loaded at once
+constexpr uint32_t kIdMask = 0x0fffffffu;  // a decrement's vertex; its top four bits carry
+constexpr int kNibShift = 28;              // the low four bits of the dying edge's id
+// Compact list bounds (owner engine): a 64-byte block per kCoffV of a
+// workgroup's vertices holds the first one's CSR offset (bit 31 set: the
+// block holds more than 255 incidences, read the offsets array instead) and
+// kCoffV + 1 one-byte offsets from it, the last being the end of the block's
+// last list.  Neighbouring frontier vertices then share far more lines than
+// in the 4-byte offsets array.  The blocks are built at the start from the
+// degrees (a workgroup scan), so building them reads nothing more.
+constexpr uint32_t kCoffV = 56;  // seven words of eight degree nibbles
+constexpr uint32_t kCoffW = kCoffV / 8;
+constexpr uint32_t kCoffIt = (kOT / kCoffW) * kCoffW;  // degree words per pass of the build
+constexpr uint32_t kCoffEsc = 0x80000000u;
 
 enum : uint32_t { kModeUndecided = 0, kModeOwnerDone = 1, kModeGlobal = 2 };
 enum : uint32_t { kRoundsAuto = 0, kRoundsDense = 1, kRoundsSparse = 2 };
@@ -103,6 +119,8 @@ struct PeelArgs {
   uint32_t *qdec;    // owner engine: R * m decrement slots, laid out by the CSR offsets
   uint32_t *stage;   // owner engine: R * (m + grid) rows of the edges won this round
   uint32_t *fbits;   // owner engine: F_t as a bitmap over the vertices (dense rounds)
+  uint32_t *coff;    // owner engine: compact list bounds, 16 words per block of kCoffV vertices
+  uint64_t coff_blocks;  // blocks that coff holds
   PeelCtrl *ctrl;
   uint64_t m;
   uint64_t limit;
@@ -114,6 +132,7 @@ struct PeelArgs {
   uint32_t force_global;  // PEEL_ENGINE=global: skip the owner engine (testing)
   uint32_t round_policy;  // PEEL_ROUNDS=sparse (default) | dense | auto (chosen per round)
   uint32_t subtables;     // 1: peeling with subtables, rounds are subrounds
+  uint32_t claims_all;    // PEEL_CLAIMS=all: owner engine without the claim filter (testing)
   uint32_t sub_lo[9];     // subtable j holds the vertices sub_lo[j] .. sub_lo[j+1]-1
 };
 
@@ -147,13 +166,24 @@ __device__ inline uint32_t nth_set_bit(uint32_t x, uint32_t r) {
   return pos + (r >= (x & 1u) ? 1u : 0u);
 }
 
-template <int R>
+// XF (the claim filter; for up to kOwnMaxVX vertices per workgroup): each
+// owned vertex also keeps, in four bits of LDS, the XOR of the low four bits
+// of the ids of its dead incident edges (every decrement carries them).  A
+// frontier vertex that holds exactly one alive edge XORs the low four bits of
+// its whole list with these, which gives the low four bits of that edge, and
+// claims only the list entries that match: the alive edge, and on average one
+// dead entry in sixteen.  Without it such a vertex claims its whole list, most
+// of which names edges that died in earlier rounds (claims of dead edges are
+// ignored by their owners, so both are exact).
+template <int R, bool XF>
 __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
+  constexpr uint32_t kV = XF ? kOwnMaxVX : kOwnMaxV;
   // Four bits per owned vertex: its degree while alive (kNib = held in the
   // global degree array instead), its removal round once removed (kNib = t >=
   // kNib, written to vertex_round directly).  `gone` marks the removed vertices.
-  __shared__ uint32_t deg4[kOwnMaxV / 8];
-  __shared__ uint32_t gone[kOwnMaxV / 32];
+  __shared__ uint32_t deg4[kV / 8];
+  __shared__ uint32_t gone[kV / 32];
+  __shared__ uint32_t dx4[XF ? kV / 8 : 1];  // XF: dead-edge id nibbles, XORed
   __shared__ uint32_t alive[kOwnMaxE / 32];
   __shared__ uint32_t claimed[kOwnMaxE / 32];  // edges claimed this round
   // Four bits per owned edge: its removal round (0 = alive; kNib = t >= kNib,
@@ -164,10 +194,10 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   __shared__ uint32_t s_start[kOT];
   __shared__ uint32_t s_pre[kOT];
   __shared__ uint32_t scan_lds[kOT / kWave + 1];
-  __shared__ uint32_t fbl[kOwnMaxV / 32];  // the next frontier, as bits over my vertices
+  __shared__ uint32_t fbl[kV / 32];        // the next frontier, as bits over my vertices
   __shared__ uint32_t sbuf[kSendChunk];    // messages sorted by destination before a send
   __shared__ uint32_t sst[kOwnMaxT];       // their starts per destination
-  __shared__ uint32_t s_n, s_w, s_p;
+  __shared__ uint32_t s_n, s_w, s_p, s_c;
 
   PeelCtrl *ctrl = a.ctrl;
   uint32_t slot, T;
@@ -177,7 +207,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   const uint32_t Vb = ((n + T - 1) / T + 31u) & ~31u;
   const uint64_t m = a.m;
   const uint32_t Eb = m ? (uint32_t)((m + T - 1) / T) : 1u;
-  if (a.force_global || T > kOwnMaxT || Vb > kOwnMaxV || Eb > kOwnMaxE) {
+  if (a.force_global || T > kOwnMaxT || Vb > kV || Eb > kOwnMaxE) {
     if (slot == 0 && threadIdx.x == 0) ctrl->mode = kModeGlobal;
     return;
   }
@@ -198,6 +228,8 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     gone[w] = 0;
     fbl[w] = 0;
   }
+  if (XF)
+    for (uint32_t w = tid; w < Vb / 8; w += kOT) dx4[w] = 0;
   for (uint32_t w = tid; w < (Eb + 31) / 32; w += kOT) {
     const uint64_t lo = e0 + 32ull * w;
     uint32_t bits = 0;
@@ -207,23 +239,65 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   }
   for (uint32_t w = tid; w < (Eb + 7) / 8; w += kOT) er4[w] = 0;
   __syncthreads();
-  for (uint32_t w = tid; w < (Vb + 7) / 8; w += kOT) {
-    uint32_t word = 0, low = 0;
+  // Degrees into LDS nibbles and F_1 into the bitmap, kCoffIt words of eight
+  // vertices a pass; the same pass writes the compact list bounds: a scan of
+  // the words' degree sums gives every vertex its offset, a block's first word
+  // writes the block's base, each word its eight bytes, a block's last word
+  // the closing byte.  They are used only if they end at offsets[v1].
+  const uint32_t nbk = (Vb + kCoffV - 1) / kCoffV;  // blocks per workgroup
+  uint32_t *myCoff = a.coff + (uint64_t)slot * nbk * 16;
+  const bool coff_fits = (uint64_t)T * nbk <= a.coff_blocks;
+  const uint32_t off0 = a.offsets[v0];
+  uint32_t run = 0;  // degree sum of my vertices before this pass
+  for (uint32_t w0 = 0; w0 < Vb / 8; w0 += kCoffIt) {
+    const uint32_t w = w0 + tid;
+    const bool mine = tid < kCoffIt && w < Vb / 8;
+    uint32_t word = 0, low = 0, sum = 0;
+    uint32_t loc[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const uint32_t v = v0 + 8 * w + i;
-      if (v < v1) {
+      loc[i] = sum;
+      if (mine && v < v1) {
         const uint32_t d = a.deg[v];
         word |= (d >= kNib ? kNib : d) << (4 * i);
         if (d < k) low |= 1u << i;
+        sum += d;
       }
     }
-    deg4[w] = word;
-    if (low) {
-      atomicOr(&fbl[w >> 2], low << (8 * (w & 3)));
-      atomicAdd(&s_p, static_cast<uint32_t>(__popc(low)));
+    if (mine) {
+      deg4[w] = word;
+      if (low) {
+        atomicOr(&fbl[w >> 2], low << (8 * (w & 3)));
+        atomicAdd(&s_p, static_cast<uint32_t>(__popc(low)));
+      }
     }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<kOT>(sum, &tot, scan_lds);
+    s_pre[tid] = ex;  // s_pre[kCoffIt] is the pass's end (kCoffIt < kOT)
+    __syncthreads();
+    if (coff_fits && mine) {
+      const uint32_t kb = tid % kCoffW, b = w / kCoffW;
+      const uint32_t bstart = s_pre[tid - kb];  // the block's first offset in this pass
+      const uint32_t bend = s_pre[tid - kb + kCoffW];
+      uint32_t *blk = myCoff + b * 16;
+      if (kb == 0) blk[0] = (off0 + run + bstart) | (bend - bstart > 255u ? kCoffEsc : 0u);
+      const uint32_t rel = ex - bstart;
+      blk[1 + 2 * kb] = ((rel + loc[0]) & 255u) | ((rel + loc[1]) & 255u) << 8 |
+                        ((rel + loc[2]) & 255u) << 16 | (rel + loc[3]) << 24;
+      blk[2 + 2 * kb] = ((rel + loc[4]) & 255u) | ((rel + loc[5]) & 255u) << 8 |
+                        ((rel + loc[6]) & 255u) << 16 | (rel + loc[7]) << 24;
+      if (kb == kCoffW - 1)
+        blk[15] = (bend - bstart) & 255u;
+      else if (w == Vb / 8 - 1)  // my last block ends early: its closing byte
+        blk[3 + 2 * kb] = (rel + sum) & 255u;
+    }
+    run += tot;
+    __syncthreads();
   }
+  if (tid == 0) s_w = (off0 + run == a.offsets[v1]) ? 1u : 0u;
+  __syncthreads();
+  const bool coff = coff_fits && s_w != 0;
   if (slot == 0)
     for (uint64_t i = tid; i < 2ull * a.max_rounds; i += kOT) a.stats[i] = 0;
   if (tid == 0) s_n = ~0u;  // F_1 is taken from the bitmap
@@ -248,20 +322,21 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       a.vr[v] = t;
     }
   };
-  // Sends the messages src[0, total) below `lim` to the queues q, at cur[d]
-  // onwards for destination d = x / per (cur[] already reserved; it advances).
+  // Sends the messages src[0, total) whose bits under `mask` are below `lim`
+  // to the queues q, at cur[d] onwards for destination d = (x & mask) / per
+  // (cur[] already reserved; it advances).
   // kSendChunk messages at a time are ranked per destination, sorted in LDS
   // and stored in sorted order, so neighbouring lanes store to neighbouring
   // places of one destination's run instead of one store per destination.
   // Uses cnt[] (free once cur[] is set).  Every thread calls it; `total` is
   // the same in every thread.
   auto sorted_send = [&](const uint32_t *src, uint32_t total, uint32_t lim, uint32_t per,
-                         uint32_t T_, uint32_t *q) {
+                         uint32_t T_, uint32_t *q, uint32_t mask) {
     if (total <= (uint32_t)kOT) {
       // a few messages (the many small rounds near and above the threshold):
       // sorting would cost more than the stores it merges
       const uint32_t x = tid < total ? src[tid] : lim;
-      if (x < lim) q[atomicAdd(&cur[x / per], 1u)] = x;
+      if ((x & mask) < lim) q[atomicAdd(&cur[(x & mask) / per], 1u)] = x;
       return;
     }
     for (uint32_t c0 = 0; c0 < total; c0 += kSendChunk) {
@@ -276,7 +351,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       }
 #pragma unroll
       for (int u = 0; u < kSendU; ++u)
-        if (x[u] < lim) rk[u] = atomicAdd(&cnt[x[u] / per], 1u);
+        if ((x[u] & mask) < lim) rk[u] = atomicAdd(&cnt[(x[u] & mask) / per], 1u);
       __syncthreads();
       uint32_t tot;
       const uint32_t ex = block_exclusive_scan<kOT>(tid < T_ ? cnt[tid] : 0u, &tot, scan_lds);
@@ -284,16 +359,22 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < kSendU; ++u)
-        if (x[u] < lim) sbuf[sst[x[u] / per] + rk[u]] = x[u];
+        if ((x[u] & mask) < lim) sbuf[sst[(x[u] & mask) / per] + rk[u]] = x[u];
       __syncthreads();
       for (uint32_t i = tid; i < tot; i += kOT) {
         const uint32_t v = sbuf[i];
-        const uint32_t d = v / per;
+        const uint32_t d = (v & mask) / per;
         q[cur[d] + (i - sst[d])] = v;
       }
       __syncthreads();
       for (uint32_t d = tid; d < T_; d += kOT) cur[d] += cnt[d];
     }
+  };
+  // The decrement for slot vertex id of dying edge e (XF: with e's low four
+  // bits on top; an id >= n is dropped)
+  auto dmsg = [&](uint32_t id, uint64_t e) -> uint32_t {
+    if (!XF) return id;
+    return id < n ? id | (static_cast<uint32_t>(e) & 15u) << kNibShift : kNoVertex;
   };
   // my edge le dies in round t (its nibble is 0 until now)
   auto mark_edge = [&](uint32_t le, uint32_t t) {
@@ -385,80 +466,124 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         mark_removed(v, v - v0, t);
       }
     }
-    // ---- sparse: one claim per incidence of every vertex of F_t that still
-    // holds an edge.  The incidence lists of up to kOT frontier vertices at a
-    // time are laid end to end (workgroup scan of their lengths) and walked one
-    // incidence per thread, so every thread's loads are independent of the
-    // list lengths.  The claims are counted per destination and kept in order
-    // in this workgroup's decrement queue, which is idle until the edge owners
-    // write it after the next barrier and is as long as my vertices' lists;
-    // then they are copied to their destinations.  The CSR is read once.
+    // ---- sparse: claims for the incidences of every vertex of F_t that still
+    // holds an edge (XF: only the matching ones of a vertex holding one).  Each
+    // wave walks its own frontier vertices, kCV per lane at a time, with no
+    // workgroup-wide step: a lane loads the list bounds of its vertices, then
+    // up to kCE incidences of each at once (the rest of a longer list is read
+    // one incidence at a time), and the wave reserves its claims' places with
+    // one LDS atomic.  The claims are counted per destination and kept in this
+    // workgroup's decrement queue, which is idle until the edge owners write it
+    // after the next barrier and is as long as my vertices' lists; then they
+    // are copied to their destinations.
     if (!over && !dense) {
       uint32_t *claims = myDecs;
       for (uint32_t d = tid; d < T; d += kOT) cnt[d] = 0;
+      if (tid == 0) s_c = 0;
       __syncthreads();
-      uint32_t nc = 0;  // claims so far (same in every thread)
-      // frontier vertex i leaves; its list's start and length (0 for a vertex
-      // of degree 0, which holds no alive edge)
-      auto take_list = [&](uint32_t i, uint32_t &st, uint32_t &len) {
-        st = 0;
-        len = 0;
-        if (i < fcnt) {
-          const uint32_t v = myF[i];
-          const uint32_t lv = v - v0;
-          const uint32_t d4 = (deg4[lv >> 3] >> (4 * (lv & 7))) & kNib;
-          mark_removed(v, lv, t);
-          if (d4 != 0) {
-            st = a.offsets[v];
-            len = a.offsets[v + 1] - st;
+      const uint32_t lane = tid & (kWave - 1);
+      // lane's vertices of the pass at b: bounds of their lists, and the low
+      // bits to match (16 = claim every entry)
+      auto head = [&](uint32_t b, uint32_t *st, uint32_t *len, uint32_t *want) {
+#pragma unroll
+        for (int u = 0; u < kCV; ++u) {
+          const uint32_t i = b + (uint32_t)u * kWave + lane;
+          st[u] = 0;
+          len[u] = 0;
+          want[u] = 16;
+          if (i < fcnt) {
+            const uint32_t v = myF[i];
+            const uint32_t lv = v - v0;
+            const uint32_t d4 = (deg4[lv >> 3] >> (4 * (lv & 7))) & kNib;
+            if (XF && d4 == 1) want[u] = (dx4[lv >> 3] >> (4 * (lv & 7))) & 15u;
+            mark_removed(v, lv, t);
+            if (d4 != 0) {  // a vertex of degree 0 holds no alive edge
+              if (coff) {
+                const uint32_t b = lv / kCoffV, q = 4 + lv - b * kCoffV;
+                const uint32_t *blk = myCoff + b * 16;
+                const uint32_t w0 = blk[0], wa = blk[q >> 2], wb = blk[(q + 1) >> 2];
+                const uint32_t la = (wa >> (8 * (q & 3))) & 255u;
+                const uint32_t lb = (wb >> (8 * ((q + 1) & 3))) & 255u;
+                st[u] = (w0 & ~kCoffEsc) + la;
+                len[u] = lb - la;
+                if (w0 & kCoffEsc) {
+                  st[u] = a.offsets[v];
+                  len[u] = a.offsets[v + 1] - st[u];
+                }
+              } else {
+                st[u] = a.offsets[v];
+                len[u] = a.offsets[v + 1] - st[u];
+              }
+            }
           }
         }
       };
-      uint32_t st, len;
-      take_list(tid, st, len);
-      for (uint32_t c0 = 0; c0 < fcnt; c0 += kOT) {
-        uint32_t tot;
-        const uint32_t ex = block_exclusive_scan<kOT>(len, &tot, scan_lds);
-        s_start[tid] = st;
-        s_pre[tid] = ex;
-        __syncthreads();
-        // the next chunk's offsets are loaded now, so that their latency
-        // overlaps that of this chunk's incidence loads
-        take_list(c0 + kOT + tid, st, len);
-        for (uint32_t j0 = tid; j0 < tot; j0 += kLU * kOT) {
-          uint32_t e[kLU];
+      constexpr uint32_t kStride = kOT * kCV;
+      uint32_t st[kCV], len[kCV], want[kCV];
+      head((tid - lane) * kCV, st, len, want);
+      for (uint32_t b = (tid - lane) * kCV; b < fcnt; b += kStride) {
+        uint32_t e[kCV][kCE];
 #pragma unroll
-          for (int u = 0; u < kLU; ++u) {
-            const uint32_t j = j0 + u * kOT;
-            e[u] = kNoVertex;
-            if (j < tot) {
-              // the last list whose start is <= j holds incidence j
-              uint32_t lo = 0, hi = kOT;
-              while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_pre[mid] <= j) lo = mid; else hi = mid;
-              }
-              e[u] = a.inc[s_start[lo] + (j - s_pre[lo])];
-            }
+        for (int u = 0; u < kCV; ++u)
+#pragma unroll
+          for (int j = 0; j < kCE; ++j) e[u][j] = (uint32_t)j < len[u] ? a.inc[st[u] + j] : 0u;
+        // the next pass's list bounds load while this pass's lists do
+        uint32_t st2[kCV], len2[kCV], want2[kCV];
+        head(b + kStride, st2, len2, want2);
+        uint32_t mine = 0;  // my claims in this pass
+#pragma unroll
+        for (int u = 0; u < kCV; ++u) {
+          if (!XF || want[u] == 16) {
+            mine += len[u];
+            continue;
           }
+          // the whole list's low bits, XORed with the dead ones': the alive edge's
+          uint32_t x = want[u];
 #pragma unroll
-          for (int u = 0; u < kLU; ++u) {
-            const uint32_t j = j0 + u * kOT;
-            if (j < tot) {
-              claims[nc + j] = e[u];
-              atomicAdd(&cnt[e[u] / Eb], 1u);
-            }
+          for (int j = 0; j < kCE; ++j)
+            if ((uint32_t)j < len[u]) x ^= e[u][j] & 15u;
+          for (uint32_t j = kCE; j < len[u]; ++j) x ^= a.inc[st[u] + j] & 15u;
+          want[u] = x;
+#pragma unroll
+          for (int j = 0; j < kCE; ++j)
+            if ((uint32_t)j < len[u] && (e[u][j] & 15u) == x) ++mine;
+          for (uint32_t j = kCE; j < len[u]; ++j)
+            if ((a.inc[st[u] + j] & 15u) == x) ++mine;
+        }
+        const uint32_t incl = wave_inclusive_scan(mine);
+        uint32_t base = 0;
+        if (lane == kWave - 1 && incl) base = atomicAdd(&s_c, incl);
+        uint32_t pos = __shfl(base, kWave - 1, kWave) + incl - mine;
+        auto claim = [&](uint32_t x) {
+          claims[pos++] = x;
+          atomicAdd(&cnt[x / Eb], 1u);
+        };
+#pragma unroll
+        for (int u = 0; u < kCV; ++u) {
+#pragma unroll
+          for (int j = 0; j < kCE; ++j)
+            if ((uint32_t)j < len[u] && (want[u] == 16 || (e[u][j] & 15u) == want[u]))
+              claim(e[u][j]);
+          for (uint32_t j = kCE; j < len[u]; ++j) {
+            const uint32_t x = a.inc[st[u] + j];
+            if (want[u] == 16 || (x & 15u) == want[u]) claim(x);
           }
         }
-        nc += tot;
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kCV; ++u) {
+          st[u] = st2[u];
+          len[u] = len2[u];
+          want[u] = want2[u];
+        }
       }
+      __syncthreads();
+      const uint32_t nc = s_c;
       for (uint32_t d = tid; d < T; d += kOT) {
         const uint32_t c = cnt[d];
         cur[d] = c ? d * Eb * R + atomicAdd(&ctrl->qh_claim[d], c) : 0u;
       }
       __syncthreads();
-      sorted_send(claims, nc, (uint32_t)m, Eb, T, a.qclaim);
+      sorted_send(claims, nc, (uint32_t)m, Eb, T, a.qclaim, ~0u);
     }
     // The barrier sums |F_t| and, in subtables mode, the number of workgroups
     // that still hold waiting bits (high word).  The barrier carries 48 bits:
@@ -528,7 +653,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
             mark_edge(le, t);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-              myStage[(uint64_t)w * R + j] = ids[u][j];
+              myStage[(uint64_t)w * R + j] = dmsg(ids[u][j], e0 + le);
               if (ids[u][j] < n) atomicAdd(&cnt[ids[u][j] / Vb], 1u);
             }
           }
@@ -560,7 +685,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
           for (int q = 0; q < R; ++q) ids[q] = row[q];
 #pragma unroll
           for (int q = 0; q < R; ++q) {
-            myStage[(uint64_t)w * R + q] = ids[q];
+            myStage[(uint64_t)w * R + q] = dmsg(ids[q], e);
             if (ids[q] < n) atomicAdd(&cnt[ids[q] / Vb], 1u);
           }
         }
@@ -622,7 +747,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
             mark_edge((uint32_t)(e[u] - e0), t);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-              myStage[(uint64_t)(won + j) * R + q] = ids[u][q];
+              myStage[(uint64_t)(won + j) * R + q] = dmsg(ids[u][q], e[u]);
               if (ids[u][q] < n) atomicAdd(&cnt[ids[u][q] / Vb], 1u);
             }
           }
@@ -640,7 +765,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       cur[d] = c ? a.offsets[dv] + atomicAdd(&ctrl->qh_dec[d], c) : 0u;
     }
     __syncthreads();
-    sorted_send(myStage, won * R, n, Vb, T, a.qdec);
+    sorted_send(myStage, won * R, n, Vb, T, a.qdec, XF ? kIdMask : ~0u);
     uint64_t et;
     if (!sum_barrier(&ctrl->bar, T, slot, won, &epoch, a.limit, &et, ctrl->stamp)) return;
     if (slot == 0 && tid == 0) a.stats[2ull * (t - 1) + 1] = et;
@@ -664,12 +789,13 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       }
 #pragma unroll
       for (int q = 0; q < kLU; ++q) {
-        const uint32_t u = us[q];
-        if (u == kNoVertex) continue;
+        if (us[q] == kNoVertex) continue;
+        const uint32_t u = XF ? us[q] & kIdMask : us[q];
         const uint32_t lv = u - v0;
         // a vertex removed this round (its edges die with it) keeps its round
         if ((gone[lv >> 5] >> (lv & 31)) & 1u) continue;
         const uint32_t sh = 4 * (lv & 7);
+        if (XF) atomicXor(&dx4[lv >> 3], (us[q] >> kNibShift) << sh);
         uint32_t old;
         if (((deg4[lv >> 3] >> sh) & kNib) == kNib)
           old = atomicSub(&a.deg[u], 1u);
@@ -875,7 +1001,8 @@ __global__ void k_peel_finish(const PeelCtrl *ctrl, const uint64_t *stats, uint3
 }
 
 struct Layout {
-  size_t ctrl, fa, fb, qclaim, qdec, stage, fbits, total;
+  size_t ctrl, fa, fb, qclaim, qdec, stage, fbits, coff, total;
+  uint64_t coff_blocks;
 };
 
 Layout layout(uint32_t n, uint64_t m, uint32_t r) {
@@ -888,7 +1015,10 @@ Layout layout(uint32_t n, uint64_t m, uint32_t r) {
   L.qdec = align_up((size_t)r * m * 4 + 4);
   L.stage = align_up((size_t)r * (m + g) * 4);
   L.fbits = align_up(((size_t)n + 31) / 32 * 4 + 4);
-  L.total = L.ctrl + L.fa + L.fb + L.qclaim + L.qdec + L.stage + L.fbits;
+  // T workgroups of ceil(Vb / kCoffV) blocks, Vb <= n / T + 32: at most n / kCoffV + 2T
+  L.coff_blocks = (uint64_t)n / kCoffV + 2 * g + 2;
+  L.coff = align_up((size_t)L.coff_blocks * 64);
+  L.total = L.ctrl + L.fa + L.fb + L.qclaim + L.qdec + L.stage + L.fbits + L.coff;
   return L;
 }
 
@@ -897,8 +1027,14 @@ peel_status launch(PeelArgs &a, hipStream_t s) {
   const DeviceInfo &dev = device_info();
   // owner engine: one workgroup per CU (its LDS use allows no more)
   const unsigned og = static_cast<unsigned>(dev.cus < (int)kOwnMaxT ? dev.cus : (int)kOwnMaxT);
-  if (dev.debug) std::fprintf(stderr, "[peel] owner grid %u\n", og);
-  hipLaunchKernelGGL(k_peel_owner<R>, dim3(og), dim3(kOT), 0, s, a);
+  // the claim filter's LDS fits when each workgroup owns at most kOwnMaxVX vertices
+  const uint64_t vb = (((uint64_t)a.n + og - 1) / og + 31) & ~31ull;
+  const bool xf = vb <= kOwnMaxVX && !a.claims_all;
+  if (dev.debug) std::fprintf(stderr, "[peel] owner grid %u, claim filter %d\n", og, (int)xf);
+  if (xf)
+    hipLaunchKernelGGL((k_peel_owner<R, true>), dim3(og), dim3(kOT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_peel_owner<R, false>), dim3(og), dim3(kOT), 0, s, a);
   PEEL_HIP_TRY(hipGetLastError());
   // global engine: runs only if the owner engine declined
   const void *fn = reinterpret_cast<const void *>(&k_peel_persistent<R>);
@@ -954,6 +1090,9 @@ peel_status peel_run(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n, 
   a.stage = reinterpret_cast<uint32_t *>(base);
   base += L.stage;
   a.fbits = reinterpret_cast<uint32_t *>(base);
+  base += L.fbits;
+  a.coff = reinterpret_cast<uint32_t *>(base);
+  a.coff_blocks = L.coff_blocks;
   a.edges = edges;
   a.offsets = offsets;
   a.inc = inc;
@@ -976,6 +1115,8 @@ peel_status peel_run(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n, 
                    : std::strcmp(rounds, "auto") == 0  ? kRoundsAuto
                                                         : kRoundsSparse;
   a.subtables = subtables ? 1u : 0u;
+  const char *claims = std::getenv("PEEL_CLAIMS");
+  a.claims_all = (claims && std::strcmp(claims, "all") == 0) ? 1u : 0u;
   a.sub_lo[0] = 0;
   for (uint32_t j = 0; j < 8; ++j)
     a.sub_lo[j + 1] = a.sub_lo[j] + (j < r ? n / r + (j < n % r ? 1u : 0u) : 0u);

@@ -46,12 +46,18 @@ def _check_against_oracle(n, edges, k, res, max_rounds=1 << 20):
     return o
 
 
-@pytest.fixture(params=["default", "dense", "auto"])
+@pytest.fixture(params=["default", "dense", "auto", "unfiltered"])
 def rounds(request, monkeypatch):
     """Which rounds the owner engine runs: the default (all sparse: claims over the
-    CSR), all dense (edge scan against the frontier bitmap), or chosen per round."""
+    CSR, filtered by the dead-edge nibbles), all dense (edge scan against the
+    frontier bitmap), chosen per round, or sparse with every incidence of a
+    frontier vertex claimed (the kernel that larger vertex ranges take)."""
+    monkeypatch.delenv("PEEL_CLAIMS", raising=False)
     if request.param == "default":
         monkeypatch.delenv("PEEL_ROUNDS", raising=False)
+    elif request.param == "unfiltered":
+        monkeypatch.delenv("PEEL_ROUNDS", raising=False)
+        monkeypatch.setenv("PEEL_CLAIMS", "all")
     else:
         monkeypatch.setenv("PEEL_ROUNDS", request.param)
     return request.param
@@ -233,11 +239,16 @@ def test_full_size_near_threshold(c):
     _check_against_oracle(spec.n, e, spec.k, res)
 
 
-@pytest.mark.parametrize("c,mode", [(0.70, "dense"), (0.85, "auto")])
+@pytest.mark.parametrize("c,mode", [(0.70, "dense"), (0.85, "auto"), (0.70, "unfiltered"),
+                                    (0.772, "unfiltered")])
 def test_full_size_forced_round_kind(c, mode, monkeypatch):
-    # every round of one kind at full size: both kinds give the oracle's answer
+    # every round of one kind at full size, and sparse rounds without the claim
+    # filter: each gives the oracle's answer
     need_gpu()
-    monkeypatch.setenv("PEEL_ROUNDS", mode)
+    if mode == "unfiltered":
+        monkeypatch.setenv("PEEL_CLAIMS", "all")
+    else:
+        monkeypatch.setenv("PEEL_ROUNDS", mode)
     spec = configs.kcore_sweep(c)
     e = spec.edges(1)
     say(spec.name, "rounds", mode)
