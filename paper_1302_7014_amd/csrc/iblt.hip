@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
   }
 
   auto stage = [&](uint64_t x, uint32_t c, uint32_t parity) {
-    const uint32_t pos = atomicAdd(&s_own, 1u);
+    const uint32_t pos = wave_append(true, &s_own);
     if (pos < cb) {
       myKeys[pos] = x;
       myOwn[pos] = c;
@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(kLT) k_list_persistent(ListArgs a) {
     // can push a cell again each time its count lands on +-1: past N places
     // the cell is dropped and the call reports PEEL_FLAG_ENOSPC.
     auto push = [&](uint32_t c) {
-      const uint32_t pos = atomicAdd(&s_cand, 1u);
+      const uint32_t pos = wave_append(true, &s_cand);
       if (pos < cb) {
         myCand[pos] = c;
       } else {
@@ -755,7 +755,7 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
     for (uint32_t i = tid; i < a.max_rounds; i += kLT) a.stats[i] = 0;
   __syncthreads();
   auto take = [&](uint64_t ks, uint32_t c) {
-    const uint32_t pos = atomicAdd(&s_own, 1u);
+    const uint32_t pos = wave_append(true, &s_own);
     myKeys[pos] = ks;
     myOwn[pos] = c;
   };
@@ -966,7 +966,7 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
         uint4 *p = reinterpret_cast<uint4 *>(a.cells + sl.cell);
         p[0] = x0[u];
         *reinterpret_cast<uint2 *>(p + 1) = x1[u];
-        if (now == 1) myCand[atomicAdd(&s_cand, 1u)] = sl.cell;
+        if (now == 1) myCand[wave_append(true, &s_cand)] = sl.cell;
       }
       __syncthreads();
     }
@@ -1037,7 +1037,7 @@ __global__ void __launch_bounds__(kLT) k_list_sub(ListArgs a) {
   uint32_t *queue[2] = {a.ocand, a.ocand + N};
 
   auto stage = [&](uint64_t x, uint32_t c, uint32_t parity) {
-    const uint32_t pos = atomicAdd(&s_own, 1u);
+    const uint32_t pos = wave_append(true, &s_own);
     if (pos < cb) {
       myKeys[pos] = x;
       myOwn[pos] = c;
@@ -1080,7 +1080,7 @@ __global__ void __launch_bounds__(kLT) k_list_sub(ListArgs a) {
     }
     __syncthreads();
     auto lpush = [&](uint32_t c) {
-      const uint32_t p = atomicAdd(&s_lq, 1u);
+      const uint32_t p = wave_append(true, &s_lq);
       if (p < (uint32_t)kLQ)
         lq[p] = c;
       else
@@ -1379,7 +1379,7 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
     detect_cells<R, false>(
         h, cells, 0, N, tid, NT, [](uint64_t i) { return static_cast<uint32_t>(i); },
         [&](uint64_t ks, uint32_t c) {
-          const uint32_t pos = atomicAdd(&s_k, 1u);
+          const uint32_t pos = wave_append(true, &s_k);
           if (pos < N) own[pos] = c;
           if (listed + pos < out_cap) out[listed + pos] = ks;
         },
@@ -1406,7 +1406,7 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
     }
     __syncthreads();
     apply_exclusive<R, NT>(h, cells, out + listed, own, K, hset,
-                           [&](uint32_t c) { cand[atomicAdd(&s_c, 1u)] = c; });
+                           [&](uint32_t c) { cand[wave_append(true, &s_c)] = c; });
     __syncthreads();
     listed += K;
     const uint32_t nc = s_c;
@@ -1417,7 +1417,7 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
     detect_cells<R, false>(
         h, cells, 0, nc, tid, NT, [&](uint64_t i) { return cand[i]; },
         [&](uint64_t ks, uint32_t c) {
-          const uint32_t pos = atomicAdd(&s_k, 1u);
+          const uint32_t pos = wave_append(true, &s_k);
           own[pos] = c;
           if (listed + pos < out_cap) out[listed + pos] = ks;
         },
@@ -1480,7 +1480,7 @@ __device__ void list_table_team(const Hash &h, iblt_cell *cells, uint32_t N, uin
       uint64_t ks, hs;
       load_cell(cells + c, &cnt, &ks, &hs);
       local += cnt;
-      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) own[atomicAdd(&s_k, 1u)] = c;
+      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) own[wave_append(true, &s_k)] = c;
     }
     if (bad) s_bad = 1;
     atomicAdd(&s_sum, (unsigned long long)local);
@@ -1527,7 +1527,7 @@ __device__ void list_table_team(const Hash &h, iblt_cell *cells, uint32_t N, uin
     if (tid == 0) s_c = 0;
     __syncthreads();
     for (uint32_t i = tid; i < mine; i += NT)
-      delete_key<R>(h, cells, out[base + i], own[i], [&](uint32_t c) { cand[atomicAdd(&s_c, 1u)] = c; });
+      delete_key<R>(h, cells, out[base + i], own[i], [&](uint32_t c) { cand[wave_append(true, &s_c)] = c; });
     listed += K;
     if (!grid_barrier(&tc->bar, Gt, limit)) {
       ok = false;
@@ -1542,7 +1542,7 @@ __device__ void list_table_team(const Hash &h, iblt_cell *cells, uint32_t N, uin
       int32_t cnt;
       uint64_t ks, hs;
       load_cell(cells + c, &cnt, &ks, &hs);
-      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) own[atomicAdd(&s_k, 1u)] = c;
+      if (owns<R>(h, cells, c, cnt, ks, hs, &bad)) own[wave_append(true, &s_k)] = c;
     }
     if (bad) s_bad = 1;
   }
@@ -1632,7 +1632,7 @@ __device__ void list_table_lds(const Hash &h, iblt_cell *cells, uint32_t N, uint
     uint32_t bad = 0;
     for (uint32_t c = tid; c < N; c += NT) {
       if (owns_lds<R>(h, T, c, &bad)) {
-        const uint32_t pos = atomicAdd(&s_k, 1u);
+        const uint32_t pos = wave_append(true, &s_k);
         T.own[pos] = static_cast<uint16_t>(c);
         if (pos < out_cap) out[pos] = T.ks[c];
       }
@@ -1669,7 +1669,7 @@ __device__ void list_table_lds(const Hash &h, iblt_cell *cells, uint32_t N, uint
         const int32_t old = atomicSub(&T.cnt[c], 1);
         atomicXor(reinterpret_cast<unsigned long long *>(&T.ks[c]), (unsigned long long)x);
         atomicXor(reinterpret_cast<unsigned long long *>(&T.hs[c]), (unsigned long long)hx);
-        if (old == 2) T.cand[atomicAdd(&s_c, 1u)] = static_cast<uint16_t>(c);
+        if (old == 2) T.cand[wave_append(true, &s_c)] = static_cast<uint16_t>(c);
       }
     }
     __syncthreads();
@@ -1689,7 +1689,7 @@ __device__ void list_table_lds(const Hash &h, iblt_cell *cells, uint32_t N, uint
     for (uint32_t i = tid; i < nc; i += NT) {
       const uint32_t c = T.cand[i];
       if (owns_lds<R>(h, T, c, &bad)) {
-        const uint32_t pos = atomicAdd(&s_k, 1u);
+        const uint32_t pos = wave_append(true, &s_k);
         T.own[pos] = static_cast<uint16_t>(c);
         if (listed + pos < out_cap) out[listed + pos] = T.ks[c];
       }

@@ -248,10 +248,27 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   uint32_t *myCoff = a.coff + (uint64_t)slot * nbk * 16;
   const bool coff_fits = (uint64_t)T * nbk <= a.coff_blocks;
   const uint32_t off0 = a.offsets[v0];
-  uint32_t run = 0;  // degree sum of my vertices before this pass
+  uint32_t run = 0;   // degree sum of my vertices before this pass
+  uint32_t nlow = 0;  // my vertices below k
+  // the degrees of my word of the pass at w0 (0 past my range); the next
+  // pass's load while this pass scans
+  auto load_deg = [&](uint32_t w0, uint32_t *dg) {
+    const uint32_t w = w0 + tid;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t v = v0 + 8 * w + i;
+      dg[i] = tid < kCoffIt && w < Vb / 8 && v < v1 ? a.deg[v] : 0u;
+    }
+  };
+  uint32_t dnext[8];
+  load_deg(0, dnext);
   for (uint32_t w0 = 0; w0 < Vb / 8; w0 += kCoffIt) {
     const uint32_t w = w0 + tid;
     const bool mine = tid < kCoffIt && w < Vb / 8;
+    uint32_t dg[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) dg[i] = dnext[i];
+    load_deg(w0 + kCoffIt, dnext);
     uint32_t word = 0, low = 0, sum = 0;
     uint32_t loc[8];
 #pragma unroll
@@ -259,7 +276,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       const uint32_t v = v0 + 8 * w + i;
       loc[i] = sum;
       if (mine && v < v1) {
-        const uint32_t d = a.deg[v];
+        const uint32_t d = dg[i];
         word |= (d >= kNib ? kNib : d) << (4 * i);
         if (d < k) low |= 1u << i;
         sum += d;
@@ -267,10 +284,8 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     }
     if (mine) {
       deg4[w] = word;
-      if (low) {
-        atomicOr(&fbl[w >> 2], low << (8 * (w & 3)));
-        atomicAdd(&s_p, static_cast<uint32_t>(__popc(low)));
-      }
+      if (low) atomicOr(&fbl[w >> 2], low << (8 * (w & 3)));
+      nlow += __popc(low);
     }
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<kOT>(sum, &tot, scan_lds);
@@ -295,7 +310,11 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     run += tot;
     __syncthreads();
   }
-  if (tid == 0) s_w = (off0 + run == a.offsets[v1]) ? 1u : 0u;
+  nlow = block_sum<kOT>(nlow, scan_lds);
+  if (tid == 0) {
+    s_w = (off0 + run == a.offsets[v1]) ? 1u : 0u;
+    s_p = nlow;
+  }
   __syncthreads();
   const bool coff = coff_fits && s_w != 0;
   if (slot == 0)
@@ -376,14 +395,33 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
     if (!XF) return id;
     return id < n ? id | (static_cast<uint32_t>(e) & 15u) << kNibShift : kNoVertex;
   };
-  // my edge le dies in round t (its nibble is 0 until now)
-  auto mark_edge = [&](uint32_t le, uint32_t t) {
+  // my edge le dies in round t; its nibble held cn until now (the claim
+  // marking's note, else 0)
+  auto mark_edge = [&](uint32_t le, uint32_t t, uint32_t cn) {
     const uint32_t sh = 4 * (le & 7);
-    if (t < kNib) {
-      atomicOr(&er4[le >> 3], t << sh);
-    } else {
-      atomicOr(&er4[le >> 3], kNib << sh);
-      a.er[e0 + le] = t;
+    atomicXor(&er4[le >> 3], ((t < kNib ? t : kNib) ^ cn) << sh);
+    if (t >= kNib) a.er[e0 + le] = t;
+  };
+  // Stages the decrements of dying edge e (row ids) at stage slot w; the slot
+  // whose vertex's low four bits are cn (the one claimer's) is skipped when it
+  // is the only such slot: that vertex leaves this round and would ignore it.
+  auto stage_row = [&](uint32_t w, uint64_t e, const uint32_t *ids, uint32_t cn) {
+    uint32_t skip = R;
+    if (cn < kNib) {
+      uint32_t hits = 0;
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if ((ids[q] & 15u) == cn) {
+          skip = q;
+          ++hits;
+        }
+      if (hits != 1) skip = R;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const bool send = (uint32_t)q != skip && ids[q] < n;
+      myStage[(uint64_t)w * R + q] = send ? dmsg(ids[q], e) : kNoVertex;
+      if (send) atomicAdd(&cnt[ids[q] / Vb], 1u);
     }
   };
 
@@ -496,6 +534,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
             const uint32_t lv = v - v0;
             const uint32_t d4 = (deg4[lv >> 3] >> (4 * (lv & 7))) & kNib;
             if (XF && d4 == 1) want[u] = (dx4[lv >> 3] >> (4 * (lv & 7))) & 15u;
+            want[u] |= (v & 15u) << 5;  // the claimer's low bits ride on its claims
             mark_removed(v, lv, t);
             if (d4 != 0) {  // a vertex of degree 0 holds no alive edge
               if (coff) {
@@ -530,20 +569,22 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         // the next pass's list bounds load while this pass's lists do
         uint32_t st2[kCV], len2[kCV], want2[kCV];
         head(b + kStride, st2, len2, want2);
+        // want[u]: bits 0-4 the low bits to match (16 = all), bits 5-8 the
+        // claimer's low bits
         uint32_t mine = 0;  // my claims in this pass
 #pragma unroll
         for (int u = 0; u < kCV; ++u) {
-          if (!XF || want[u] == 16) {
+          if (!XF || (want[u] & 31u) == 16) {
             mine += len[u];
             continue;
           }
           // the whole list's low bits, XORed with the dead ones': the alive edge's
-          uint32_t x = want[u];
+          uint32_t x = want[u] & 15u;
 #pragma unroll
           for (int j = 0; j < kCE; ++j)
             if ((uint32_t)j < len[u]) x ^= e[u][j] & 15u;
           for (uint32_t j = kCE; j < len[u]; ++j) x ^= a.inc[st[u] + j] & 15u;
-          want[u] = x;
+          want[u] = (want[u] & ~31u) | x;
 #pragma unroll
           for (int j = 0; j < kCE; ++j)
             if ((uint32_t)j < len[u] && (e[u][j] & 15u) == x) ++mine;
@@ -554,19 +595,20 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         uint32_t base = 0;
         if (lane == kWave - 1 && incl) base = atomicAdd(&s_c, incl);
         uint32_t pos = __shfl(base, kWave - 1, kWave) + incl - mine;
-        auto claim = [&](uint32_t x) {
-          claims[pos++] = x;
+        auto claim = [&](uint32_t x, uint32_t wnt) {
+          claims[pos++] = x | (wnt >> 5) << kNibShift;
           atomicAdd(&cnt[x / Eb], 1u);
         };
 #pragma unroll
         for (int u = 0; u < kCV; ++u) {
+          const uint32_t wl = want[u] & 31u;
 #pragma unroll
           for (int j = 0; j < kCE; ++j)
-            if ((uint32_t)j < len[u] && (want[u] == 16 || (e[u][j] & 15u) == want[u]))
-              claim(e[u][j]);
+            if ((uint32_t)j < len[u] && (wl == 16 || (e[u][j] & 15u) == wl))
+              claim(e[u][j], want[u]);
           for (uint32_t j = kCE; j < len[u]; ++j) {
             const uint32_t x = a.inc[st[u] + j];
-            if (want[u] == 16 || (x & 15u) == want[u]) claim(x);
+            if (wl == 16 || (x & 15u) == wl) claim(x, want[u]);
           }
         }
 #pragma unroll
@@ -583,7 +625,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
         cur[d] = c ? d * Eb * R + atomicAdd(&ctrl->qh_claim[d], c) : 0u;
       }
       __syncthreads();
-      sorted_send(claims, nc, (uint32_t)m, Eb, T, a.qclaim, ~0u);
+      sorted_send(claims, nc, (uint32_t)m, Eb, T, a.qclaim, kIdMask);
     }
     // The barrier sums |F_t| and, in subtables mode, the number of workgroups
     // that still hold waiting bits (high word).  The barrier carries 48 bits:
@@ -650,7 +692,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
           const uint32_t w = wave_append(die, &s_w);
           if (die) {
             atomicAnd(&alive[le >> 5], ~(1u << (le & 31)));
-            mark_edge(le, t);
+            mark_edge(le, t, 0u);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
               myStage[(uint64_t)w * R + j] = dmsg(ids[u][j], e0 + le);
@@ -668,26 +710,24 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
       const uint32_t nclaims = s_n;
       if (nclaims <= (uint32_t)kOT) {
         // few claims: one per thread, in arrival order
-        uint32_t e = 0;
+        uint32_t e = 0, cn = kNib;
         bool win = false;
         if (tid < nclaims) {
-          e = myClaims[tid];
+          const uint32_t c = myClaims[tid];
+          e = c & kIdMask;
+          cn = c >> kNibShift;
           const uint32_t le = e - (uint32_t)e0;
           const uint32_t bit = 1u << (le & 31);
           win = (atomicAnd(&alive[le >> 5], ~bit) & bit) != 0;
         }
         const uint32_t w = wave_append(win, &s_w);
         if (win) {
-          mark_edge(e - (uint32_t)e0, t);
+          mark_edge(e - (uint32_t)e0, t, 0u);
           const uint32_t *row = a.edges + (uint64_t)e * R;
           uint32_t ids[R];
 #pragma unroll
           for (int q = 0; q < R; ++q) ids[q] = row[q];
-#pragma unroll
-          for (int q = 0; q < R; ++q) {
-            myStage[(uint64_t)w * R + q] = dmsg(ids[q], e);
-            if (ids[q] < n) atomicAdd(&cnt[ids[q] / Vb], 1u);
-          }
+          stage_row(w, e, ids, cn);  // cn: this claim's claimer, which leaves now
         }
         __syncthreads();
         won = s_w;
@@ -699,11 +739,17 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
           const uint32_t i = i0 + u * kOT;
           e[u] = i < nclaims ? myClaims[i] : kNoVertex;
         }
+        // a claim of an alive edge sets its claimed bit and notes the
+        // claimer's low bits in the edge's round nibble (0 while alive); a
+        // second claim makes the note kNib (no slot skipped)
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
           if (e[u] == kNoVertex) continue;
-          const uint32_t le = e[u] - (uint32_t)e0;
-          atomicOr(&claimed[le >> 5], 1u << (le & 31));
+          const uint32_t le = (e[u] & kIdMask) - (uint32_t)e0;
+          const uint32_t bit = 1u << (le & 31);
+          if (!(alive[le >> 5] & bit)) continue;
+          const uint32_t first = !(atomicOr(&claimed[le >> 5], bit) & bit);
+          atomicOr(&er4[le >> 3], (first ? e[u] >> kNibShift : kNib) << (4 * (le & 7)));
         }
       }
       __syncthreads();
@@ -744,12 +790,10 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
           for (int u = 0; u < kEU; ++u) {
             const uint32_t j = j0 + u * kOT;
             if (j >= tot) continue;
-            mark_edge((uint32_t)(e[u] - e0), t);
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-              myStage[(uint64_t)(won + j) * R + q] = dmsg(ids[u][q], e[u]);
-              if (ids[u][q] < n) atomicAdd(&cnt[ids[u][q] / Vb], 1u);
-            }
+            const uint32_t le = (uint32_t)(e[u] - e0);
+            const uint32_t cn = (er4[le >> 3] >> (4 * (le & 7))) & kNib;
+            mark_edge(le, t, cn);
+            stage_row(won + j, e[u], ids[u], cn);
           }
         }
         won += tot;
@@ -803,7 +847,7 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
           old = (atomicSub(&deg4[lv >> 3], 1u << sh) >> sh) & kNib;
         if (old == k) {
           atomicOr(&fbl[lv >> 5], 1u << (lv & 31));
-          const uint32_t p = atomicAdd(&s_n, 1u);
+          const uint32_t p = wave_append(true, &s_n);  // the lanes here
           if (p < (uint32_t)kOT) s_start[p] = u;
         }
       }
