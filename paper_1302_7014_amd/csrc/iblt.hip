@@ -679,6 +679,7 @@ constexpr uint32_t kMC = 2048;      // messages sorted in LDS at a time
 constexpr uint32_t kOAC = 2048;     // messages combined in LDS at a time
 constexpr uint32_t kOHBits = 12;
 constexpr uint32_t kOHS = 1u << kOHBits;  // hash slots for one apply chunk
+constexpr uint32_t kSeenMax = 98304;      // owned cells the LDS bitmaps of the listing cover
 static_assert(2 * kOAC <= kOHS, "the apply's hash table stays at most half full");
 
 struct OwnArgs {
@@ -690,6 +691,7 @@ struct OwnArgs {
   uint64_t *keys;   // N: the keys each owner lists this round (at its first cell)
   uint32_t *ownc;   // N: the cells they were listed from
   uint32_t *cand;   // N: each owner's candidates for the next round
+  uint64_t *candk;  // N: their keys (a candidate is pushed pure: count 1, checksum good)
   uint4 *msg;       // (r-1) N: each owner's outgoing messages {cell, 0, key lo, key hi}
   uint32_t *mcnt;   // grid x grid: messages from owner s to owner d at [s * grid + d]
   uint32_t *moff;   // grid x grid: where in s's region they start
@@ -724,6 +726,13 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
   __shared__ uint32_t scan_lds[kLT / kWave + 1];
   __shared__ uint32_t s_own, s_cand, s_bad;
   __shared__ unsigned long long s_sum;
+  // apply: my cells updated in this round's apply (seen) and those updated in
+  // two of its chunks (multi), whose pushed value may be stale
+  __shared__ uint32_t seen[kSeenMax / 32];
+  __shared__ uint32_t multi[kSeenMax / 32];
+  // my cells whose key has been listed: cleared once, in cell order, at the end
+  // (no later round reads such a cell: it held that key alone)
+  __shared__ uint32_t listed_at[kSeenMax / 32];
 
   ListCtrl *ctrl = a.ctrl;
   uint32_t slot, T;
@@ -734,13 +743,58 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
     if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_TIMEOUT);
     return;
   }
-  const uint32_t cr = (N + T - 1) / T;
-  const uint32_t c0 = slot * cr < N ? slot * cr : N;
-  const uint32_t c1 = c0 + cr < N ? c0 + cr : N;
-  uint64_t *myKeys = a.keys + c0;
-  uint32_t *myOwn = a.ownc + c0;
-  uint32_t *myCand = a.cand + c0;
-  uint4 *myMsg = a.msg + (uint64_t)(R - 1) * c0;
+  // My cells: the slot-th piece of every subtable (pieces of pw[j] cells).
+  // An owner of only low-subtable cells would have no ownership tests to make
+  // and most of the round-1 keys to list, and one of only high-subtable cells
+  // the opposite; a piece of each balances every phase across the team.
+  uint32_t pw[R], plo[R], pn[R];
+  uint32_t cw = 0, nmine = 0;  // cells per workgroup at most, and mine
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const uint32_t sz = static_cast<uint32_t>(a.h.size[j]);
+    pw[j] = (sz + T - 1) / T;
+    const uint32_t lo = slot * pw[j] < sz ? slot * pw[j] : sz;
+    const uint32_t hi = lo + pw[j] < sz ? lo + pw[j] : sz;
+    plo[j] = static_cast<uint32_t>(a.h.base[j]) + lo;
+    pn[j] = hi - lo;
+    cw += pw[j];
+    nmine += pn[j];
+  }
+  // the owner of cell c of subtable j
+  auto owner = [&](int j, uint32_t c) {
+    return (c - static_cast<uint32_t>(a.h.base[j])) / pw[j];
+  };
+  // my i-th cell, i < nmine
+  auto my_cell = [&](uint64_t i) {
+    uint32_t k = static_cast<uint32_t>(i), c = 0;
+    bool found = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (!found && k < pn[j]) {
+        c = plo[j] + k;
+        found = true;
+      }
+      if (!found) k -= pn[j];
+    }
+    return c;
+  };
+  // the place of my cell c among my cells
+  auto my_index = [&](uint32_t c) {
+    uint32_t k = 0, r = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (c >= plo[j] && c < plo[j] + pn[j]) r = k + (c - plo[j]);
+      k += pn[j];
+    }
+    return r;
+  };
+  const bool track = nmine <= kSeenMax;  // else every candidate is read back, and
+                                         // a listed key's cell is cleared at once
+  uint64_t *myKeys = a.keys + (uint64_t)slot * cw;
+  uint32_t *myOwn = a.ownc + (uint64_t)slot * cw;
+  uint32_t *myCand = a.cand + (uint64_t)slot * cw;
+  uint64_t *myCandK = a.candk + (uint64_t)slot * cw;
+  uint4 *myMsg = a.msg + (uint64_t)(R - 1) * slot * cw;
   uint4 *sbuf = reinterpret_cast<uint4 *>(pool);
   uint16_t *sdst = reinterpret_cast<uint16_t *>(pool + kMC * sizeof(uint4));
   OwnSlot *hslot = reinterpret_cast<OwnSlot *>(pool);
@@ -753,6 +807,8 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
   }
   if (slot == 0)
     for (uint32_t i = tid; i < a.max_rounds; i += kLT) a.stats[i] = 0;
+  if (track)
+    for (uint32_t w = tid; w < (nmine + 31) / 32; w += kLT) listed_at[w] = 0;
   __syncthreads();
   auto take = [&](uint64_t ks, uint32_t c) {
     const uint32_t pos = wave_append(true, &s_own);
@@ -763,9 +819,7 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
   {
     long long local = 0;
     uint32_t bad = 0;
-    detect_cells<R, false>(
-        h, a.cells, c0, c1, tid, kLT, [](uint64_t i) { return static_cast<uint32_t>(i); }, take,
-        &bad, &local);
+    detect_cells<R, false>(h, a.cells, 0, nmine, tid, kLT, my_cell, take, &bad, &local);
     if (bad) s_bad = 1;
     atomicAdd(&s_sum, (unsigned long long)local);
   }
@@ -784,7 +838,7 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
       const uint32_t jo = subtable_of(h, myOwn[i]);
 #pragma unroll
       for (int j = 0; j < R; ++j)
-        if ((uint32_t)j != jo) atomicAdd(&cnt[cell_of(h, j, x) / cr], 1u);
+        if ((uint32_t)j != jo) atomicAdd(&cnt[owner(j, cell_of(h, j, x))], 1u);
     }
     __syncthreads();
     uint32_t base = 0;
@@ -815,7 +869,7 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         cl[j] = cell_of(h, j, x);
-        if (live && (uint32_t)j != jo) rk[j] = atomicAdd(&cnt[cl[j] / cr], 1u);
+        if (live && (uint32_t)j != jo) rk[j] = atomicAdd(&cnt[owner(j, cl[j])], 1u);
       }
       __syncthreads();
       uint32_t tot = 0, run = 0;
@@ -832,7 +886,7 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           if ((uint32_t)j == jo) continue;
-          const uint32_t d = cl[j] / cr;
+          const uint32_t d = owner(j, cl[j]);
           const uint32_t p = sst[d] + rk[j];
           sbuf[p] = make_uint4(cl[j], 0u, static_cast<uint32_t>(x), static_cast<uint32_t>(x >> 32));
           sdst[p] = static_cast<uint16_t>(d);
@@ -868,7 +922,12 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
     // ---- apply ---------------------------------------------------------------
     for (uint32_t i = tid; i < nk; i += kLT) {
       a.out[listed + prefix + i] = myKeys[i];
-      clear_cell(a.cells + myOwn[i]);
+      if (track) {
+        const uint32_t lc = my_index(myOwn[i]);
+        atomicOr(&listed_at[lc >> 5], 1u << (lc & 31));
+      } else {
+        clear_cell(a.cells + myOwn[i]);
+      }
     }
     // the runs addressed to me, one per sender, laid end to end
     uint32_t nin = 0;
@@ -887,6 +946,8 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
       inpre[T] = nin;
       s_cand = 0;
     }
+    if (track)
+      for (uint32_t w = tid; w < (nmine + 31) / 32; w += kLT) seen[w] = multi[w] = 0;
     __syncthreads();
     // kOAC messages a chunk, kOU per thread.  A chunk's messages were loaded
     // during the previous chunk, and each thread loads the cells of its
@@ -906,7 +967,7 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
           const uint32_t mid = (lo + hi) >> 1;
           if (inpre[mid] <= i) lo = mid; else hi = mid;
         }
-        mm[u] = a.msg[(uint64_t)(R - 1) * (lo * cr) + sst[lo] + (i - inpre[lo])];
+        mm[u] = a.msg[(uint64_t)(R - 1) * lo * cw + sst[lo] + (i - inpre[lo])];
       }
     };
     uint4 mnext[kOU];
@@ -966,7 +1027,20 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
         uint4 *p = reinterpret_cast<uint4 *>(a.cells + sl.cell);
         p[0] = x0[u];
         *reinterpret_cast<uint2 *>(p + 1) = x1[u];
-        if (now == 1) myCand[wave_append(true, &s_cand)] = sl.cell;
+        // A cell that went to count 1 is pushed with its key.  The detect
+        // trusts that value unless the cell is marked multi: updated by two
+        // chunks of this apply (the value may be stale), or pushed with a
+        // checksum that does not match (the detect reads it back and judges).
+        const uint32_t lc = track ? my_index(sl.cell) : 0u, bit = 1u << (lc & 31);
+        if (track && (atomicOr(&seen[lc >> 5], bit) & bit)) atomicOr(&multi[lc >> 5], bit);
+        if (now == 1) {
+          const uint64_t ks = (uint64_t)x0[u].z | ((uint64_t)x0[u].w << 32);
+          const uint64_t hs = (uint64_t)x1[u].x | ((uint64_t)x1[u].y << 32);
+          if (track && hs != check_of(h, ks)) atomicOr(&multi[lc >> 5], bit);
+          const uint32_t pos = wave_append(true, &s_cand);
+          myCand[pos] = sl.cell;
+          myCandK[pos] = ks;
+        }
       }
       __syncthreads();
     }
@@ -981,11 +1055,36 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
     }
     __syncthreads();
     {
+      // a candidate not marked multi is pure with the pushed key: only the
+      // ownership test reads the table; a marked one is read back
       uint32_t bad = 0;
-      long long unused = 0;
-      detect_cells<R, false>(
-          h, a.cells, 0, ncand, tid, kLT, [&](uint64_t i) { return myCand[i]; }, take, &bad,
-          &unused);
+      for (uint32_t ib = tid; ib < ncand; ib += kDetU * kLT) {
+        uint32_t c[kDetU];
+        int32_t cn[kDetU];
+        uint64_t ks[kDetU], hs[kDetU];
+#pragma unroll
+        for (int u = 0; u < kDetU; ++u) {
+          const uint32_t i = ib + (uint32_t)u * kLT;
+          c[u] = 0;
+          cn[u] = 0;
+          ks[u] = hs[u] = 0;
+          if (i < ncand) {
+            c[u] = myCand[i];
+            ks[u] = myCandK[i];
+            const uint32_t lc = track ? my_index(c[u]) : 0u;
+            if (!track || ((multi[lc >> 5] >> (lc & 31)) & 1u)) {
+              load_cell(a.cells + c[u], &cn[u], &ks[u], &hs[u]);
+            } else {
+              cn[u] = 1;
+              hs[u] = check_of(h, ks[u]);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kDetU; ++u)
+          if (ib + (uint32_t)u * kLT < ncand && owns<R, false>(h, a.cells, c[u], cn[u], ks[u], hs[u], &bad))
+            take(ks[u], c[u]);
+      }
       if (bad) s_bad = 1;
     }
     __syncthreads();
@@ -994,6 +1093,12 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
     send(nk);
     if (!sum_barrier(&ctrl->bar, T, slot, nk, &epoch, a.limit, &total, ctrl->stamp, &prefix))
       return;
+  }
+  // the cells my listed keys came from, cleared in cell order
+  if (track) {
+    __syncthreads();
+    for (uint32_t lc = tid; lc < nmine; lc += kLT)
+      if ((listed_at[lc >> 5] >> (lc & 31)) & 1u) clear_cell(a.cells + my_cell(lc));
   }
   if (slot == 0 && tid == 0) {
     ctrl->rounds = t - 1 < a.max_rounds ? t - 1 : a.max_rounds;
@@ -2079,13 +2184,15 @@ bool list_first_binned_fits(const iblt_desc *d) {
   return d->workgroups == 0 && d->ncells >= kListBinnedMin && upd_binned(d, d->ncells);
 }
 
-// The owner engine's arrays: keys, their cells and the candidates (one entry
-// per cell), (r-1) 16-byte messages per cell, and the owners' message tables.
+// The owner engine's arrays: keys, their cells, the candidates and their keys (one
+// entry per cell), (r-1) 16-byte messages per cell, and the owners' message tables.
+// A team of T workgroups owns pieces of ceil(size_j / T) cells of each
+// subtable: T * sum_j ceil(size_j / T) <= N + r * T places in all.
 size_t owner_ws_bytes(const iblt_desc *d) {
   const ListLayout L = list_layout(d->ncells, d->workgroups);
-  const uint64_t N = d->ncells, g = L.grid;
-  return L.ctrl + align_up(N * 8) + 2 * align_up(N * 4) + align_up((uint64_t)(d->r - 1) * N * 16) +
-         2 * align_up(g * g * 4);
+  const uint64_t g = L.grid, N = d->ncells + (uint64_t)d->r * g;
+  return L.ctrl + 2 * align_up(N * 8) + 2 * align_up(N * 4) +
+         align_up((uint64_t)(d->r - 1) * N * 16) + 2 * align_up(g * g * 4);
 }
 
 size_t list_ws_bytes(const iblt_desc *d) {
@@ -2189,7 +2296,7 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
     o.ncells = a.ncells;
     o.max_rounds = max_rounds;
     o.grid = L.grid;
-    const uint64_t N = desc->ncells, g = L.grid;
+    const uint64_t g = L.grid, N = desc->ncells + (uint64_t)desc->r * g;
     char *ob = static_cast<char *>(ws) + L.ctrl;
     o.keys = reinterpret_cast<uint64_t *>(ob);
     ob += align_up(N * 8);
@@ -2197,6 +2304,8 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
     ob += align_up(N * 4);
     o.cand = reinterpret_cast<uint32_t *>(ob);
     ob += align_up(N * 4);
+    o.candk = reinterpret_cast<uint64_t *>(ob);
+    ob += align_up(N * 8);
     o.msg = reinterpret_cast<uint4 *>(ob);
     ob += align_up((uint64_t)(desc->r - 1) * N * 16);
     o.mcnt = reinterpret_cast<uint32_t *>(ob);
