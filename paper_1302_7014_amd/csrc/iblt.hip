@@ -738,7 +738,6 @@ __global__ void __launch_bounds__(kLT) k_list_owner(OwnArgs a) {
   uint32_t slot, T;
   if (!team_join(&ctrl->team, a.quiet, a.team_limit, &slot, &T)) return;
   const uint32_t tid = threadIdx.x;
-  const uint32_t N = a.ncells;
   if (T > kLMaxT) {  // cannot happen: the grid is at most the CU count
     if (slot == 0 && tid == 0) atomicOr(&ctrl->flags, PEEL_FLAG_TIMEOUT);
     return;
