@@ -167,6 +167,19 @@ def test_corrupt_cell():
     check_table(cells, t)
 
 
+@pytest.mark.parametrize("r", [3, 4])
+def test_list_past_the_owners_lds_bitmaps(r, list_engine):
+    # 2^25 + 12345 cells: each of 256 owners holds ~131 K cells, more than its
+    # LDS bitmaps cover (98304), so it reads every candidate back and clears
+    # each listed key's cell at once instead of at the end
+    need_gpu()
+    ncells = (1 << 25) + 12345
+    keys = gen.distinct_keys(int(0.6 * ncells), 31 + r)
+    say("past the LDS bitmaps", list_engine, ncells, r, keys.size)
+    g, o = check_list(ncells, r, gen.table_seed(31 + r), keys)
+    assert g["listed"] == keys.size and g["left"] == 0
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
 def test_config_iblt_full_size(seed):
     # 2^24 cells, r = 3, 10,296,982 keys: every key comes back, round by round as the oracle.

@@ -172,6 +172,25 @@ def test_medium_models_bit_exact(r, k, c, rounds):
         _check_against_oracle(n, e, k, res)
 
 
+@pytest.mark.parametrize("k", [2, 3])
+def test_list_bounds_blocks_with_hub_vertices(rounds, k):
+    # a few vertices of degree ~300 among ordinary ones: the blocks of compact
+    # list bounds that hold them have more than 255 incidences and are read
+    # from the offsets array, the others from their one-byte offsets
+    need_gpu()
+    n = (1 << 16) + 77
+    rng = np.random.default_rng(12)
+    e = gen.partitioned_edges(n, int(0.7 * n), 4, 13)
+    hubs = rng.choice(n, 40, replace=False).astype(np.uint32)
+    extra = rng.integers(0, n, size=(40 * 300, 4)).astype(np.uint32)
+    extra[:, 0] = np.repeat(hubs, 300)
+    e = np.concatenate([e, extra])
+    say("hub vertices", rounds, n, e.shape, k)
+    res = gpu_peel(n, e, k)
+    assert res["flags"] == 0
+    _check_against_oracle(n, e, k, res)
+
+
 def test_round_limit_leaves_consistent_state(rounds):
     need_gpu()
     n = 1 << 16
