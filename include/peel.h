@@ -100,7 +100,8 @@ peel_status hg_build(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n,
  * of round t, and every alive edge that holds a vertex of F_t; each removed
  * edge lowers the degree of each of its r slots by one.  The run stops at the
  * first empty F_t.  An edge hit by several peeled vertices in one round dies
- * once (it is claimed by compare-and-swap on its round word).
+ * once (its owning workgroup clears its alive bit in LDS; the fallback engine
+ * claims it by compare-and-swap on its round word).
  *
  *   edges, m, r, n   as for hg_build;  k >= 1.
  *   offsets, inc     (device) the CSR from hg_build for these edges.
@@ -290,10 +291,11 @@ peel_status iblt_update(const iblt_desc *desc, iblt_cell *cells, const uint64_t 
  *                [5..7] 0.
  *   ws           (device) ws_bytes >= iblt_list_workspace(desc): about
  *                (16 r + 32) bytes per cell.
- * The rounds run in one persistent kernel.  Each workgroup owns a range of
- * cells and is their only writer: a listed key's deletions from its other
- * cells are sent to those cells' owners, which combine them and update each
- * cell with one plain read-modify-write (no device atomics).  With
+ * The rounds run in one persistent kernel.  Each workgroup owns a piece of
+ * every subtable and is the only writer of those cells: a listed key's
+ * deletions from its other cells are sent to those cells' owners, which
+ * combine them and update each cell with one plain read-modify-write (no
+ * device atomics).  With
  * PEEL_LIST_ENGINE=atomic in the environment the deletions are device
  * atomics instead (the signed listing's engine); the results are the same.
  */
