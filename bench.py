@@ -481,12 +481,14 @@ def traffic_from_profile(kernel):
     ent = doc.get(kernel)
     if not ent:
         return None
-    src = os.path.join(ROOT, ent["source"])
-    if not os.path.exists(src):
-        return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if digest != ent["source_sha256"]:
-        return None
+    # the kernel's own source and the headers it includes (barriers, scans)
+    files = {ent["source"]: ent["source_sha256"], **ent.get("deps", {})}
+    for rel, want in files.items():
+        src = os.path.join(ROOT, rel)
+        if not os.path.exists(src):
+            return None
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != want:
+            return None
     return ent["bytes_per_launch"]
 
 

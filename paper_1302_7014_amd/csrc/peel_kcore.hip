@@ -85,13 +85,16 @@ constexpr uint32_t kCoffW = kCoffV / 8;
 constexpr uint32_t kCoffIt = (kOT / kCoffW) * kCoffW;  // degree words per pass of the build
 constexpr uint32_t kCoffEsc = 0x80000000u;
 
-enum : uint32_t { kModeUndecided = 0, kModeOwnerDone = 1, kModeGlobal = 2 };
+// kModeRetry: the claim-filter kernel declined (the team that formed was too
+// small for its LDS), the owner kernel without the filter takes the run
+enum : uint32_t { kModeUndecided = 0, kModeOwnerDone = 1, kModeGlobal = 2, kModeRetry = 3 };
 enum : uint32_t { kRoundsAuto = 0, kRoundsDense = 1, kRoundsSparse = 2 };
 
 struct PeelCtrl {
   SumBar bar;          // owner engine barrier
   GridSync sync;       // global engine barrier
   Team team_own;
+  Team team_own2;  // the owner kernel without the claim filter, after kModeRetry
   Team team_glob;
   uint32_t mode;
   uint32_t fcount[3];  // global engine: |F_t| lives in fcount[t % 3]
@@ -132,7 +135,10 @@ struct PeelArgs {
   uint32_t force_global;  // PEEL_ENGINE=global: skip the owner engine (testing)
   uint32_t round_policy;  // PEEL_ROUNDS=sparse (default) | dense | auto (chosen per round)
   uint32_t subtables;     // 1: peeling with subtables, rounds are subrounds
-  uint32_t claims_all;    // PEEL_CLAIMS=all: owner engine without the claim filter (testing)
+  uint32_t claims_all;    // PEEL_CLAIMS=all: owner engine without the claim filter;
+                          // =retry: the claim-filter kernel declines as if its team
+                          // were too small (testing)
+  uint32_t retry;         // this launch runs only after the claim-filter kernel declined
   uint32_t sub_lo[9];     // subtable j holds the vertices sub_lo[j] .. sub_lo[j+1]-1
 };
 
@@ -200,15 +206,21 @@ __global__ void __launch_bounds__(kOT) k_peel_owner(PeelArgs a) {
   __shared__ uint32_t s_n, s_w, s_p, s_c;
 
   PeelCtrl *ctrl = a.ctrl;
+  if (a.retry &&
+      __hip_atomic_load(&ctrl->mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kModeRetry)
+    return;
   uint32_t slot, T;
-  if (!team_join(&ctrl->team_own, a.quiet, a.team_limit, &slot, &T)) return;
+  if (!team_join(a.retry ? &ctrl->team_own2 : &ctrl->team_own, a.quiet, a.team_limit, &slot, &T))
+    return;
   const uint32_t n = a.n;
   // vertex ranges start on 32-vertex boundaries, so bitmap slices do not share words
   const uint32_t Vb = ((n + T - 1) / T + 31u) & ~31u;
   const uint64_t m = a.m;
   const uint32_t Eb = m ? (uint32_t)((m + T - 1) / T) : 1u;
-  if (a.force_global || T > kOwnMaxT || Vb > kV || Eb > kOwnMaxE) {
-    if (slot == 0 && threadIdx.x == 0) ctrl->mode = kModeGlobal;
+  if (a.force_global || T > kOwnMaxT || Vb > kV || Eb > kOwnMaxE || (XF && a.claims_all == 2)) {
+    // a team too small for the claim filter's LDS may still fit the wider kernel
+    const bool wider = XF && !a.force_global && T <= kOwnMaxT && Vb <= kOwnMaxV && Eb <= kOwnMaxE;
+    if (slot == 0 && threadIdx.x == 0) ctrl->mode = wider ? kModeRetry : kModeGlobal;
     return;
   }
   const uint32_t tid = threadIdx.x;
@@ -1034,7 +1046,8 @@ __global__ void k_peel_finish(const PeelCtrl *ctrl, const uint64_t *stats, uint3
       break;
     }
   uint32_t flags = ctrl->flags;
-  if (ctrl->sync.abort || ctrl->bar.abort || ctrl->mode == kModeUndecided)
+  if (ctrl->sync.abort || ctrl->bar.abort || ctrl->mode == kModeUndecided ||
+      ctrl->mode == kModeRetry)
     flags |= PEEL_FLAG_TIMEOUT;
   summary[0] = rounds;
   summary[1] = last_e;
@@ -1073,12 +1086,18 @@ peel_status launch(PeelArgs &a, hipStream_t s) {
   const unsigned og = static_cast<unsigned>(dev.cus < (int)kOwnMaxT ? dev.cus : (int)kOwnMaxT);
   // the claim filter's LDS fits when each workgroup owns at most kOwnMaxVX vertices
   const uint64_t vb = (((uint64_t)a.n + og - 1) / og + 31) & ~31ull;
-  const bool xf = vb <= kOwnMaxVX && !a.claims_all;
+  const bool xf = vb <= kOwnMaxVX && a.claims_all != 1;
   if (dev.debug) std::fprintf(stderr, "[peel] owner grid %u, claim filter %d\n", og, (int)xf);
-  if (xf)
+  if (xf) {
     hipLaunchKernelGGL((k_peel_owner<R, true>), dim3(og), dim3(kOT), 0, s, a);
-  else
+    PEEL_HIP_TRY(hipGetLastError());
+    // runs only if the team that formed was too small for the claim filter
+    PeelArgs b = a;
+    b.retry = 1;
+    hipLaunchKernelGGL((k_peel_owner<R, false>), dim3(og), dim3(kOT), 0, s, b);
+  } else {
     hipLaunchKernelGGL((k_peel_owner<R, false>), dim3(og), dim3(kOT), 0, s, a);
+  }
   PEEL_HIP_TRY(hipGetLastError());
   // global engine: runs only if the owner engine declined
   const void *fn = reinterpret_cast<const void *>(&k_peel_persistent<R>);
@@ -1160,7 +1179,11 @@ peel_status peel_run(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n, 
                                                         : kRoundsSparse;
   a.subtables = subtables ? 1u : 0u;
   const char *claims = std::getenv("PEEL_CLAIMS");
-  a.claims_all = (claims && std::strcmp(claims, "all") == 0) ? 1u : 0u;
+  a.claims_all = !claims ? 0u
+                 : std::strcmp(claims, "all") == 0   ? 1u
+                 : std::strcmp(claims, "retry") == 0 ? 2u
+                                                     : 0u;
+  a.retry = 0;
   a.sub_lo[0] = 0;
   for (uint32_t j = 0; j < 8; ++j)
     a.sub_lo[j + 1] = a.sub_lo[j] + (j < r ? n / r + (j < n % r ? 1u : 0u) : 0u);

@@ -46,18 +46,19 @@ def _check_against_oracle(n, edges, k, res, max_rounds=1 << 20):
     return o
 
 
-@pytest.fixture(params=["default", "dense", "auto", "unfiltered"])
+@pytest.fixture(params=["default", "dense", "auto", "unfiltered", "retry"])
 def rounds(request, monkeypatch):
     """Which rounds the owner engine runs: the default (all sparse: claims over the
     CSR, filtered by the dead-edge nibbles), all dense (edge scan against the
-    frontier bitmap), chosen per round, or sparse with every incidence of a
-    frontier vertex claimed (the kernel that larger vertex ranges take)."""
+    frontier bitmap), chosen per round, sparse with every incidence of a
+    frontier vertex claimed (the kernel that larger vertex ranges take), or that
+    kernel taking over after the claim filter's kernel declined."""
     monkeypatch.delenv("PEEL_CLAIMS", raising=False)
     if request.param == "default":
         monkeypatch.delenv("PEEL_ROUNDS", raising=False)
-    elif request.param == "unfiltered":
+    elif request.param in ("unfiltered", "retry"):
         monkeypatch.delenv("PEEL_ROUNDS", raising=False)
-        monkeypatch.setenv("PEEL_CLAIMS", "all")
+        monkeypatch.setenv("PEEL_CLAIMS", "all" if request.param == "unfiltered" else "retry")
     else:
         monkeypatch.setenv("PEEL_ROUNDS", request.param)
     return request.param
@@ -259,13 +260,15 @@ def test_full_size_near_threshold(c):
 
 
 @pytest.mark.parametrize("c,mode", [(0.70, "dense"), (0.85, "auto"), (0.70, "unfiltered"),
-                                    (0.772, "unfiltered")])
+                                    (0.772, "unfiltered"), (0.70, "retry")])
 def test_full_size_forced_round_kind(c, mode, monkeypatch):
-    # every round of one kind at full size, and sparse rounds without the claim
-    # filter: each gives the oracle's answer
+    # every round of one kind at full size, sparse rounds without the claim
+    # filter, and the hand-over to the kernel without it when the claim
+    # filter's kernel declines (as when too small a team forms for its LDS):
+    # each gives the oracle's answer
     need_gpu()
-    if mode == "unfiltered":
-        monkeypatch.setenv("PEEL_CLAIMS", "all")
+    if mode in ("unfiltered", "retry"):
+        monkeypatch.setenv("PEEL_CLAIMS", "all" if mode == "unfiltered" else "retry")
     else:
         monkeypatch.setenv("PEEL_ROUNDS", mode)
     spec = configs.kcore_sweep(c)
