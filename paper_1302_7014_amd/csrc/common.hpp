@@ -183,9 +183,11 @@ __device__ inline bool grid_barrier(GridSync *gs, uint32_t nblocks, uint64_t lim
 // workgroup.  Members are split into up to kBarGroups groups (slot % groups);
 // each arrives on its group word (low 16 bits count arrivals, the rest sums the
 // values), the last of a group forwards the group's sum to the top word, and
-// the last group publishes the total and a new top generation.  Group leaders
-// pass the release down to their group.  Every poll is a relaxed load with a
-// short sleep.  Timeouts and `abort` behave as in grid_barrier.
+// the last group publishes the total and a new top generation.  A call that
+// wants its prefix waits for its group's leader to pass the release down (the
+// leader stores the group's base first); any other waits on the top
+// generation itself, one hop less.  Every poll is a relaxed load with a short
+// sleep.  Timeouts and `abort` behave as in grid_barrier.
 //
 // Groups.  In the first barrier of a run the groups are slots mod 16, every
 // workgroup makes its stores visible device-wide with its own release fence
@@ -306,10 +308,12 @@ __device__ inline bool sum_barrier(SumBar *sb, uint32_t nblocks, uint32_t slot, 
         __hip_atomic_store(&gp->gen, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     } else {
-      ok = bar_wait(&gp->gen, e, &sb->abort, limit);
+      // no prefix wanted: wait on the top generation itself (one hop)
+      ok = bar_wait(prefix ? &gp->gen : &sb->top_gen, e, &sb->abort, limit);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       tot = __hip_atomic_load(&sb->total[e & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      pre = __hip_atomic_load(&gp->base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + (old >> 16);
+      if (prefix)
+        pre = __hip_atomic_load(&gp->base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + (old >> 16);
     }
     if (e == 1) {
       // every member counted itself before arriving: the census is complete
