@@ -224,6 +224,12 @@ struct alignas(128) SumBar {
   BarGroup grp[kBarGroups];
 };
 
+// Called by a run's init kernel after it zeroes the barrier: with slots set,
+// the XCD census is marked unusable, so every barrier keeps the slot groups.
+__device__ inline void bar_force_slot_groups(SumBar *sb, bool slots) {
+  if (slots) sb->census_bad = 1u;
+}
+
 __device__ inline bool bar_wait(const uint32_t *gen, uint32_t e, uint32_t *abort, uint64_t limit) {
   const uint64_t t0 = wall_clock64();
   while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {

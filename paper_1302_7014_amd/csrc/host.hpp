@@ -7,6 +7,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <mutex>
 
 #include "peel.h"
@@ -77,6 +78,14 @@ inline const DeviceInfo &device_info() {
     d.id = dev;
   }
   return d;
+}
+
+// PEEL_BARRIER=slots (read at each call): every device-wide barrier of the
+// call keeps the slot groups of its first barrier, the path a team takes when
+// the XCD census does not cover it (tests).
+inline bool barrier_slots() {
+  const char *b = std::getenv("PEEL_BARRIER");
+  return b && std::strcmp(b, "slots") == 0;
 }
 
 // Device wall-clock ticks a device-wide barrier waits before the call gives

@@ -424,9 +424,11 @@ struct ListArgs {
   uint32_t first_binned;  // round 1 ran before the launch: outputs and rounds follow it
 };
 
-__global__ void k_list_init(ListCtrl *ctrl) {
+__global__ void k_list_init(ListCtrl *ctrl, uint32_t slot_groups) {
   uint32_t *w = reinterpret_cast<uint32_t *>(ctrl);
   for (uint32_t i = threadIdx.x; i < sizeof(ListCtrl) / 4; i += blockDim.x) w[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) bar_force_slot_groups(&ctrl->bar, slot_groups != 0);
 }
 
 // Claims cell c for this round's listing (signed tables: a cell can be queued
@@ -2272,7 +2274,8 @@ peel_status list_run(const iblt_desc *desc, iblt_cell *cells, uint64_t *out_keys
   if (slot_cap > 0 && (uint64_t)slot_cap < a.cb) a.cb = static_cast<uint32_t>(slot_cap);
   a.grid = L.grid;
   a.first_binned = 0;
-  hipLaunchKernelGGL(k_list_init, dim3(1), dim3(256), 0, s, a.ctrl);
+  hipLaunchKernelGGL(k_list_init, dim3(1), dim3(256), 0, s, a.ctrl,
+                     barrier_slots() ? 1u : 0u);
   PEEL_HIP_TRY(hipGetLastError());
   peel_status st;
   // The plain listing runs on the owner engine; PEEL_LIST_ENGINE=atomic (or a

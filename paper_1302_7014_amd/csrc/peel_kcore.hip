@@ -150,9 +150,11 @@ __device__ inline uint32_t subtable_of_vertex(const PeelArgs &a, uint32_t r, uin
   return j;
 }
 
-__global__ void k_peel_init(PeelCtrl *ctrl) {
+__global__ void k_peel_init(PeelCtrl *ctrl, uint32_t slot_groups) {
   uint32_t *w = reinterpret_cast<uint32_t *>(ctrl);
   for (uint32_t i = threadIdx.x; i < sizeof(PeelCtrl) / 4; i += blockDim.x) w[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) bar_force_slot_groups(&ctrl->bar, slot_groups != 0);
 }
 
 // ===========================================================================
@@ -1188,7 +1190,8 @@ peel_status peel_run(const uint32_t *edges, uint64_t m, uint32_t r, uint32_t n, 
   for (uint32_t j = 0; j < 8; ++j)
     a.sub_lo[j + 1] = a.sub_lo[j] + (j < r ? n / r + (j < n % r ? 1u : 0u) : 0u);
 
-  hipLaunchKernelGGL(k_peel_init, dim3(1), dim3(256), 0, s, a.ctrl);
+  hipLaunchKernelGGL(k_peel_init, dim3(1), dim3(256), 0, s, a.ctrl,
+                     barrier_slots() ? 1u : 0u);
   PEEL_HIP_TRY(hipGetLastError());
   peel_status st;
   switch (r) {

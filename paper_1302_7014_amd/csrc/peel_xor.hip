@@ -83,9 +83,11 @@ struct XorArgs {
   uint32_t max_rounds;
 };
 
-__global__ void k_xor_init(XorCtrl *ctrl) {
+__global__ void k_xor_init(XorCtrl *ctrl, uint32_t slot_groups) {
   uint32_t *w = reinterpret_cast<uint32_t *>(ctrl);
   for (uint32_t i = threadIdx.x; i < sizeof(XorCtrl) / 4; i += blockDim.x) w[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) bar_force_slot_groups(&ctrl->bar, slot_groups != 0);
 }
 
 __device__ inline bool bit_of(const uint32_t *bits, uint32_t v) {
@@ -554,7 +556,8 @@ extern "C" peel_status peel_k2_xor(const uint32_t *edges, uint64_t m, uint32_t r
   a.limit = barrier_limit_ticks();
   a.team_limit = device_info().team_limit_ticks;
   a.quiet = device_info().team_quiet_ticks;
-  hipLaunchKernelGGL(k_xor_init, dim3(1), dim3(256), 0, s, a.ctrl);
+  hipLaunchKernelGGL(k_xor_init, dim3(1), dim3(256), 0, s, a.ctrl,
+                     barrier_slots() ? 1u : 0u);
   hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(kBlock), 0, s, info, (uint64_t)4, 0u);
   if (m)
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(m, kBlock * 4, 4096)), dim3(kBlock), 0, s,
