@@ -244,7 +244,9 @@ __device__ inline bool bar_wait(const uint32_t *gen, uint32_t e, uint32_t *abort
 }
 
 // Returns false on timeout/abort (the caller leaves the kernel).  `epoch` is the
-// workgroup's count of barriers passed (thread 0's copy is the one used).
+// workgroup's count of barriers passed (thread 0's copy is the one used).  A
+// kernel uses one SumBar for its whole run: the XCD grouping learned in the
+// first call is kept in the workgroup's LDS for the later ones.
 // `*total` receives the sum of all values; `*prefix` (if given) the sum of the
 // values of the workgroups ordered before this one in this barrier (an
 // exclusive prefix in arrival order).
