@@ -54,6 +54,26 @@ __host__ __device__ inline Hash make_hash(const iblt_desc &d) {
   return h;
 }
 
+// make_hash for a table whose r is the compile-time R.  Every index is then a
+// constant, so a kernel that builds the hash itself keeps it in registers; with
+// a run-time r the arrays are indexed dynamically and land in scratch memory,
+// which every cell_of then reads.
+template <int R>
+__device__ inline Hash make_hash_fixed(const iblt_desc &d) {
+  Hash h{};
+  uint64_t acc = 0;
+  h.r = R;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    h.size[j] = d.ncells / R + ((uint64_t)j < d.ncells % R ? 1 : 0);
+    h.base[j] = acc;
+    acc += h.size[j];
+    h.salt[j] = splitmix64(d.seed, (uint64_t)j);
+  }
+  h.salt_c = splitmix64(d.seed, 8);
+  return h;
+}
+
 __device__ inline uint32_t cell_of(const Hash &h, uint32_t j, uint64_t x) {
   return static_cast<uint32_t>(h.base[j] + mulhi64(mix64(x ^ h.salt[j]), h.size[j]));
 }
@@ -291,9 +311,14 @@ __global__ void __launch_bounds__(kUT)
 // Sets *bad for a count-1 cell whose checksum does not match.
 // SIGNED (tables holding deletions too): a count of -1 is pure as well, and a
 // count of +-1 with a wrong checksum is an ordinary cell holding several keys.
-template <int R, bool SIGNED = false>
+// may(l) == false promises that cell l is not pure, so its read is skipped.
+struct AnyCell {
+  __device__ bool operator()(uint32_t) const { return true; }
+};
+
+template <int R, bool SIGNED = false, typename May = AnyCell>
 __device__ inline bool owns(const Hash &h, const iblt_cell *cells, uint32_t c, int32_t cnt,
-                            uint64_t ks, uint64_t hs, uint32_t *bad) {
+                            uint64_t ks, uint64_t hs, uint32_t *bad, May may = May()) {
   if (cnt != 1 && !(SIGNED && cnt == -1)) return false;
   const uint64_t hx = check_of(h, ks);
   if (hs != hx) {
@@ -304,9 +329,11 @@ __device__ inline bool owns(const Hash &h, const iblt_cell *cells, uint32_t c, i
 #pragma unroll
   for (int i = 0; i < R - 1; ++i) {
     if (i >= (int)j) break;
+    const uint32_t l = cell_of(h, i, ks);
+    if (!may(l)) continue;
     int32_t oc;
     uint64_t ok, oh;
-    load_cell(cells + cell_of(h, i, ks), &oc, &ok, &oh);
+    load_cell(cells + l, &oc, &ok, &oh);
     if ((oc == 1 || (SIGNED && oc == -1)) && ok == ks && oh == hx) return false;
   }
   return true;
@@ -316,12 +343,12 @@ __device__ inline bool owns(const Hash &h, const iblt_cell *cells, uint32_t c, i
 // below i1.  kDetU cells per lane are loaded before any is tested, so a lane has
 // kDetU loads in flight: with one, a scan of a table in HBM is bound by load
 // latency rather than bandwidth.  take(key, cell) gets every owned key; *sum
-// gets the counts of the cells read.
+// gets the counts of the cells read.  may: as for owns.
 constexpr int kDetU = 4;
-template <int R, bool SIGNED, typename At, typename Take>
+template <int R, bool SIGNED, typename At, typename Take, typename May = AnyCell>
 __device__ inline void detect_cells(const Hash &h, const iblt_cell *cells, uint64_t i0, uint64_t i1,
                                     uint32_t tid, uint32_t nt, At cell_at, Take take,
-                                    uint32_t *bad, long long *sum) {
+                                    uint32_t *bad, long long *sum, May may = May()) {
   for (uint64_t ib = i0 + tid; ib < i1; ib += (uint64_t)kDetU * nt) {
     uint32_t c[kDetU];
     int32_t cnt[kDetU];
@@ -340,7 +367,7 @@ __device__ inline void detect_cells(const Hash &h, const iblt_cell *cells, uint6
 #pragma unroll
     for (int u = 0; u < kDetU; ++u) {
       *sum += cnt[u];  // 0 for the places past i1
-      if (ib + (uint64_t)u * nt < i1 && owns<R, SIGNED>(h, cells, c[u], cnt[u], ks[u], hs[u], bad))
+      if (ib + (uint64_t)u * nt < i1 && owns<R, SIGNED>(h, cells, c[u], cnt[u], ks[u], hs[u], bad, may))
         take(ks[u], c[u]);
     }
   }
@@ -1458,17 +1485,54 @@ __device__ void apply_exclusive(const Hash &h, iblt_cell *cells, const uint64_t 
   }
 }
 
+// The in-place schedule's ownership filter: one LDS bit per cell of the lower
+// subtables (the cells below base[R-1], the only ones an owner test reads),
+// folded modulo the bits there are when the table has more such cells.  A
+// clear bit promises that the cell is not pure at the start of the round, so
+// the owner test skips its HBM read; a set bit only says it may be.
+//   - Round 1 scans the subtables in order and marks the cells that own their
+//     key: when subtable j is tested, every lower pure cell that can decide a
+//     test (the key's lowest pure cell) is marked.
+//   - Round t > 1: a cell pure at the start of the round went 2 -> 1 in round
+//     t - 1's apply (every cell pure at the start of t - 1 lost its key in
+//     t - 1, and counts only fall), and the apply marks every such push.
+// The bits are cleared before each apply.  Skipped reads change no result: the
+// test only ever returns false on a cell of count 1 whose checksum matches.
+struct OwnFilter {
+  uint32_t *w;
+  uint32_t nbits;  // min(lower, bits in w)
+  uint32_t lower;  // cells of the lower subtables
+  __device__ uint32_t slot(uint32_t c) const { return c < nbits ? c : c % nbits; }
+  __device__ bool operator()(uint32_t c) const {
+    const uint32_t q = slot(c);
+    return (w[q >> 5] >> (q & 31)) & 1u;
+  }
+  __device__ void mark(uint32_t c) const {
+    if (c >= lower) return;
+    const uint32_t q = slot(c);
+    atomicOr(&w[q >> 5], 1u << (q & 31));
+  }
+  __device__ void clear(uint32_t tid, uint32_t nt) const {
+    for (uint32_t q = tid; q < (nbits + 31) / 32; q += nt) w[q] = 0;
+  }
+};
+
 // Lists one table with one NT-thread workgroup.  cand and own are scratch of
-// ncells entries each.  Writes the table's outputs like iblt_list.
+// ncells entries each; filt is LDS of filt_words words.  Writes the table's
+// outputs like iblt_list.
 template <int R, int NT>
-__device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, uint64_t *out,
+__device__ __forceinline__ void list_table_block(const iblt_desc desc, iblt_cell *cells, uint32_t N, uint64_t *out,
                                  uint64_t out_cap, uint64_t *stats, uint32_t max_rounds,
                                  uint64_t *summary, uint32_t *cand, uint32_t *own,
-                                 uint32_t *hset) {
+                                 uint32_t *hset, uint32_t *filt, uint32_t filt_words) {
+  const Hash h = make_hash_fixed<R>(desc);
   __shared__ uint32_t s_k, s_c, s_bad, s_flags;
   __shared__ unsigned long long s_sum;
   const uint32_t tid = threadIdx.x;
+  const uint32_t lower = static_cast<uint32_t>(h.base[R - 1]);
+  const OwnFilter f{filt, lower < 32u * filt_words ? lower : 32u * filt_words, lower};
   for (uint32_t i = tid; i < max_rounds; i += NT) stats[i] = 0;
+  f.clear(tid, NT);
   if (tid == 0) {
     s_k = 0;
     s_bad = 0;
@@ -1477,19 +1541,30 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
   }
   __syncthreads();
   uint64_t listed = 0;
-  // round-1 detect over every cell: owned keys go straight to out[listed + pos]
+  // round-1 detect over every cell, one subtable after another: owned keys go
+  // straight to out[listed + pos], and their cells are marked
   {
     long long local = 0;
     uint32_t bad = 0;
-    // kDetU cells per lane in flight (detect_cells)
-    detect_cells<R, false>(
-        h, cells, 0, N, tid, NT, [](uint64_t i) { return static_cast<uint32_t>(i); },
-        [&](uint64_t ks, uint32_t c) {
-          const uint32_t pos = wave_append(true, &s_k);
-          if (pos < N) own[pos] = c;
-          if (listed + pos < out_cap) out[listed + pos] = ks;
-        },
-        &bad, &local);
+    // subtable j is [j q + min(j, m), (j + 1) q + min(j + 1, m)), as make_hash
+    // lays them out (q = N / R, m = N % R)
+    const uint32_t q = N / R, m = N % R;
+    for (uint32_t j = 0; j < (uint32_t)R; ++j) {
+      const uint32_t lo = j * q + (j < m ? j : m);
+      const uint32_t hi = lo + q + (j < m ? 1u : 0u);
+      // kDetU cells per lane in flight (detect_cells)
+      detect_cells<R, false>(
+          h, cells, lo, hi, tid, NT,
+          [](uint64_t i) { return static_cast<uint32_t>(i); },
+          [&](uint64_t ks, uint32_t c) {
+            const uint32_t pos = wave_append(true, &s_k);
+            if (pos < N) own[pos] = c;
+            if (listed + pos < out_cap) out[listed + pos] = ks;
+            f.mark(c);
+          },
+          &bad, &local, f);
+      if (j + 1 < (uint32_t)R) __syncthreads();
+    }
     if (bad) s_bad = 1;
     atomicAdd(&s_sum, (unsigned long long)local);
   }
@@ -1510,9 +1585,12 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
       stats[t - 1] = K;
       s_c = 0;
     }
+    f.clear(tid, NT);
     __syncthreads();
-    apply_exclusive<R, NT>(h, cells, out + listed, own, K, hset,
-                           [&](uint32_t c) { cand[wave_append(true, &s_c)] = c; });
+    apply_exclusive<R, NT>(h, cells, out + listed, own, K, hset, [&](uint32_t c) {
+      cand[wave_append(true, &s_c)] = c;
+      f.mark(c);
+    });
     __syncthreads();
     listed += K;
     const uint32_t nc = s_c;
@@ -1527,7 +1605,7 @@ __device__ void list_table_block(const Hash &h, iblt_cell *cells, uint32_t N, ui
           own[pos] = c;
           if (listed + pos < out_cap) out[listed + pos] = ks;
         },
-        &bad, &unused);
+        &bad, &unused, f);
     if (bad) s_bad = 1;
     __syncthreads();
   }
@@ -1561,10 +1639,11 @@ struct TeamCtrl {
 static_assert(sizeof(TeamCtrl) == 64, "one line per table");
 
 template <int R, int NT>
-__device__ void list_table_team(const Hash &h, iblt_cell *cells, uint32_t N, uint64_t *out,
+__device__ void list_table_team(const iblt_desc desc, iblt_cell *cells, uint32_t N, uint64_t *out,
                                 uint64_t out_cap, uint64_t *stats, uint32_t max_rounds,
                                 uint64_t *summary, uint32_t *cand, uint32_t *own, uint32_t g,
                                 uint32_t Gt, TeamCtrl *tc, uint64_t limit) {
+  const Hash h = make_hash_fixed<R>(desc);
   __shared__ uint32_t s_k, s_c, s_bad, s_pos;
   __shared__ unsigned long long s_sum;
   const uint32_t tid = threadIdx.x;
@@ -1706,9 +1785,10 @@ __device__ inline bool owns_lds(const Hash &h, const LdsTable &T, uint32_t c, ui
 }
 
 template <int R, int NT>
-__device__ void list_table_lds(const Hash &h, iblt_cell *cells, uint32_t N, uint64_t *out,
+__device__ void list_table_lds(const iblt_desc desc, iblt_cell *cells, uint32_t N, uint64_t *out,
                                uint64_t out_cap, uint64_t *stats, uint32_t max_rounds,
                                uint64_t *summary, LdsTable &T) {
+  const Hash h = make_hash_fixed<R>(desc);
   __shared__ uint32_t s_k, s_c, s_bad, s_flags;
   __shared__ unsigned long long s_sum;
   const uint32_t tid = threadIdx.x;
@@ -1829,18 +1909,26 @@ struct BatchCtrl {
 };
 
 // first/teams: null when the team schedule is off (a work unit is then a table).
+// LDS words of one batched-listing workgroup.  Registers hold a CU to one
+// 1024-thread, two 512-thread or four 256-thread workgroups (three with the
+// LDS table, 48 KiB); each size takes what leaves that many in 160 KiB.
+template <int NT, bool LDS>
+constexpr uint32_t kBatchLdsWords = NT == 1024 ? 32768u : NT == 512 ? 19968u : LDS ? 12288u : 9984u;
+
 template <int NT, bool LDS>
 __global__ void __launch_bounds__(NT)
     k_list_batched(const iblt_batch_entry *entries, uint32_t ntables, uint32_t max_rounds,
                    BatchCtrl *ctrl, uint32_t *scratch, uint64_t max_cells, uint32_t lds_max,
                    const uint32_t *first, TeamCtrl *teams, uint64_t limit) {
   __shared__ uint32_t s_t;
-  __shared__ typename std::conditional<LDS, LdsTable, uint32_t>::type lt;
-  // the in-place apply's hash set: the LDS table's space when there is one
-  __shared__ uint32_t hset_own[LDS ? 1 : kApplySet<NT>];
-  static_assert(!LDS || sizeof(LdsTable) >= kApplySet<NT> * sizeof(uint32_t),
-                "the hash set fits in the LDS table");
-  uint32_t *hset = LDS ? reinterpret_cast<uint32_t *>(&lt) : hset_own;
+  // the LDS-resident table, or the in-place schedule's hash set and filter
+  __shared__ __align__(16) uint32_t region[kBatchLdsWords<NT, LDS>];
+  static_assert(!LDS || sizeof(LdsTable) <= sizeof(region), "the LDS table fits");
+  static_assert(kBatchLdsWords<NT, LDS> >= kApplySet<NT> + 1024, "the filter has room");
+  LdsTable &lt = *reinterpret_cast<LdsTable *>(region);
+  uint32_t *hset = region;
+  uint32_t *filt = region + kApplySet<NT>;
+  constexpr uint32_t filt_words = kBatchLdsWords<NT, LDS> - kApplySet<NT>;
   uint32_t *cand = scratch + (uint64_t)blockIdx.x * 2 * max_cells;
   uint32_t *own = cand + max_cells;
   __shared__ uint32_t s_g, s_gt;
@@ -1866,7 +1954,10 @@ __global__ void __launch_bounds__(NT)
       s_gt = gt;
     }
     __syncthreads();
-    const uint32_t ti = s_t, g = s_g, gt = s_gt;
+    // the same in every lane: read once, so the entry and its hash are scalar
+    const uint32_t ti = __builtin_amdgcn_readfirstlane(s_t);
+    const uint32_t g = __builtin_amdgcn_readfirstlane(s_g);
+    const uint32_t gt = __builtin_amdgcn_readfirstlane(s_gt);
     __syncthreads();
     if (ti >= ntables) return;
     const iblt_batch_entry e = entries[ti];
@@ -1876,12 +1967,11 @@ __global__ void __launch_bounds__(NT)
       if (e.summary && threadIdx.x < 8) e.summary[threadIdx.x] = threadIdx.x == 3 ? PEEL_FLAG_EINVAL : 0u;
       continue;
     }
-    const Hash h = make_hash(e.desc);
     const uint32_t N = static_cast<uint32_t>(e.desc.ncells);
     if (gt > 1) {
 #define PEEL_TEAM_CASE(RR)                                                                        \
   case RR:                                                                                        \
-    list_table_team<RR, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds,     \
+    list_table_team<RR, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds,     \
                             e.summary, cand, own, g, gt, teams + ti, limit);                      \
     break;
       switch (e.desc.r) {
@@ -1899,7 +1989,7 @@ __global__ void __launch_bounds__(NT)
     if constexpr (LDS) {
       if (N <= lds_max) {
 #define PEEL_LDS_CASE(RR) \
-  case RR: list_table_lds<RR, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, lt); break;
+  case RR: list_table_lds<RR, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, lt); break;
         switch (e.desc.r) {
           PEEL_LDS_CASE(2)
           PEEL_LDS_CASE(3)
@@ -1907,20 +1997,20 @@ __global__ void __launch_bounds__(NT)
           PEEL_LDS_CASE(5)
           PEEL_LDS_CASE(6)
           PEEL_LDS_CASE(7)
-          default: list_table_lds<8, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, lt); break;
+          default: list_table_lds<8, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, lt); break;
         }
 #undef PEEL_LDS_CASE
         continue;
       }
     }
     switch (e.desc.r) {
-      case 2: list_table_block<2, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
-      case 3: list_table_block<3, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
-      case 4: list_table_block<4, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
-      case 5: list_table_block<5, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
-      case 6: list_table_block<6, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
-      case 7: list_table_block<7, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
-      default: list_table_block<8, NT>(h, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset); break;
+      case 2: list_table_block<2, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset, filt, filt_words); break;
+      case 3: list_table_block<3, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset, filt, filt_words); break;
+      case 4: list_table_block<4, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset, filt, filt_words); break;
+      case 5: list_table_block<5, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset, filt, filt_words); break;
+      case 6: list_table_block<6, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset, filt, filt_words); break;
+      case 7: list_table_block<7, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset, filt, filt_words); break;
+      default: list_table_block<8, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, cand, own, hset, filt, filt_words); break;
     }
   }
 }
