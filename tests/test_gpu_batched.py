@@ -90,6 +90,29 @@ def test_batched_matches_oracle(threads, lds):
 
 
 @pytest.mark.parametrize("threads", [256, 1024])
+def test_in_place_filter_folds(threads):
+    # The in-place schedule's ownership filter has one LDS bit per lower-subtable
+    # cell up to 360,448 bits (256 threads) or 917,504 (1024 threads); these
+    # tables have more lower cells than that, so cells share bits (a shared bit
+    # only costs a read).  One is above threshold, so a core remains.
+    need_gpu()
+    c3, c4 = theory.cstar(2, 3)[0], theory.cstar(2, 4)[0]
+    specs = [(1_500_000, 3, int(0.80 * c3 * 1_500_000), 41),
+             (1_300_001, 4, int(0.90 * c4 * 1_300_001), 42),
+             (1_400_000, 3, int(1.05 * c3 * 1_400_000), 43),
+             (800_003, 2, int(0.45 * 800_003), 44),
+             (600_000, 3, int(0.75 * c3 * 600_000), 45)]
+    tables, keys, _ = _make_tables(specs, 256)
+    ent = pk.batch_entries(tables, "cuda")
+    say("batched filter folds", len(tables), "threads", threads)
+    pk.iblt_list_batched(ent, len(tables), max(x[0] for x in specs), 256, block_threads=threads,
+                         lds_max_cells=0)
+    torch.cuda.synchronize()
+    for t, k in zip(tables, keys):
+        _check_against_oracle(t, k, 256)
+
+
+@pytest.mark.parametrize("threads", [256, 1024])
 def test_lds_schedule_edges(threads):
     # LDS-resident tables at the size limit and around it, above threshold (a core
     # remains), a tiny round limit, a tiny output capacity and a corrupt cell.
