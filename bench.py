@@ -553,7 +553,7 @@ def main():
                     help="of the batched workloads, only the 4096-table batch")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched listing with the schedule the tuner picks for the 4096-table "
-                         "batch (1024 threads, LDS tables up to 2048 cells), no tuning runs "
+                         "batch (1024 threads, LDS tables up to 5120 cells), no tuning runs "
                          "(profiles of one schedule)")
     ap.add_argument("--iblt-main", action="store_true",
                     help="of the IBLT workloads, only the 2^24-cell main one (profiles of one shape)")

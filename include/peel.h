@@ -359,9 +359,11 @@ peel_status iblt_list_subtables(const iblt_desc *desc, iblt_cell *cells, uint64_
  * barriers only.  Sorting `entries` by decreasing ncells balances the load.
  *
  * Three per-table schedules exist, chosen by size class:
- *   - a table of at most `lds_max_cells` cells is read once into the
- *     workgroup's local memory (LDS), listed there with LDS atomics, and
- *     written back;
+ *   - a table of at most `lds_max_cells` cells that fits the workgroup's
+ *     local memory (LDS) is read once into it, listed there with LDS
+ *     atomics, and written back.  A workgroup of 1024 threads holds up to
+ *     IBLT_LDS_MAX_CELLS = 5120 cells, one of 512 up to 3072, one of 256 up
+ *     to 2048; a larger table is listed in place;
  *   - a table of at least `tile_min_cells` cells (with tile_workgroups >= 2)
  *     is listed by a team of tile_workgroups workgroups of the same launch:
  *     member g detects the g-th slice of the cells in round 1 and then the
@@ -391,7 +393,7 @@ peel_status iblt_list_subtables(const iblt_desc *desc, iblt_cell *cells, uint64_
  * null or not 32-byte aligned is not listed: its summary (if not null) gets
  * [3] = PEEL_FLAG_EINVAL and zeros elsewhere, and the other tables go on.
  */
-#define IBLT_LDS_MAX_CELLS 2048u
+#define IBLT_LDS_MAX_CELLS 5120u
 
 typedef struct iblt_batch_schedule {
     uint32_t block_threads;   /* threads per workgroup: 256, 512, 1024; 0 = 512  */

@@ -7,7 +7,7 @@ The HIP kernels live in ``libpeel.so`` behind the C ABI of ``include/peel.h``;
 from .binding import (  # noqa: F401
     EXPORTS, FLAG_ECORRUPT, FLAG_EINVAL, FLAG_ENOSPC, FLAG_ERANGE, FLAG_EROUNDS, FLAG_ETEAM,
     FLAG_TIMEOUT,
-    IBLT_LDS_MAX_CELLS, IBLT_NOALLOC_MAX_CELLS, BatchSchedule, BatchTable, Csr, IbltDesc,
+    IBLT_LDS_CELLS, IBLT_LDS_MAX_CELLS, IBLT_NOALLOC_MAX_CELLS, BatchSchedule, BatchTable, Csr, IbltDesc,
     ListOut, PeelError, PeelOut, SignedListOut, batch_entries, batch_table, hg_build,
     hg_build_workspace, iblt_delete, iblt_desc, iblt_insert, iblt_list, iblt_list_batched,
     iblt_list_batched_noalloc, iblt_list_batched_workspace, iblt_list_signed, iblt_list_workspace,

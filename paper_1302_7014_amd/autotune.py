@@ -7,8 +7,9 @@ other table is listed in place by one workgroup.  Which schedule wins depends
 on the table sizes and on how many tables share the GPU, so the tuner times
 the candidates on the caller's own tables, one size class at a time:
 
-- small tables (at most ``IBLT_LDS_MAX_CELLS`` cells): LDS-resident or in
-  place, for each thread count;
+- small tables (at most ``IBLT_LDS_MAX_CELLS`` cells): LDS-resident (as far
+  as the thread count's LDS holds them, ``IBLT_LDS_CELLS``) or in place, for
+  each thread count;
 - medium tables: in place, for each thread count;
 - large tables (at least ``LARGE_MIN`` cells): one workgroup each, or teams
   of 2 to 32 workgroups, for each thread count.

@@ -361,7 +361,9 @@ def iblt_list_batched_workspace(ntables: int, max_cells: int) -> int:
     return int(lib().iblt_list_batched_workspace(ntables, max_cells))
 
 
-IBLT_LDS_MAX_CELLS = 2048
+IBLT_LDS_MAX_CELLS = 5120
+# the most cells a workgroup of each size lists from LDS; a larger table is listed in place
+IBLT_LDS_CELLS = {256: 2048, 512: 3072, 1024: 5120}
 
 
 class BatchSchedule(C.Structure):
@@ -378,7 +380,8 @@ def iblt_list_batched(entries: torch.Tensor, ntables: int, max_cells: int, max_r
     """List every table of a batch in one launch (entries from ``batch_entries``).
 
     ``lds_max_cells``: tables of at most this many cells are listed from LDS
-    (None = the library default, IBLT_LDS_MAX_CELLS; 0 = never).  Tables of at
+    (None = the library default, IBLT_LDS_MAX_CELLS; 0 = never), as far as the
+    workgroup size holds them (IBLT_LDS_CELLS).  Tables of at
     least ``tile_min_cells`` cells are listed by teams of ``tile_workgroups``
     workgroups (0 or 1 = no teams)."""
     if ws is None:

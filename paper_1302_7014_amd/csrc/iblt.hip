@@ -1755,18 +1755,24 @@ __device__ void list_table_team(const iblt_desc desc, iblt_cell *cells, uint32_t
 // apply run on it with LDS atomics, and the final cells are written back.
 // Same rounds and key sets as the in-place schedule.
 
-constexpr uint32_t kLdsCells = IBLT_LDS_MAX_CELLS;
+// The most cells an NT-thread workgroup lists from LDS: what its share of the
+// CU's LDS holds at 24 bytes a cell (kBatchLdsWords below).
+template <int NT>
+constexpr uint32_t kLdsCap = NT == 1024 ? 5120u : NT == 512 ? 3072u : 2048u;
+constexpr uint32_t kLdsCells = kLdsCap<1024>;
+static_assert(kLdsCells == IBLT_LDS_MAX_CELLS, "the header's limit is the largest capacity");
 
+template <uint32_t Cap>
 struct LdsTable {
-  int32_t cnt[kLdsCells];
-  uint64_t ks[kLdsCells];
-  uint64_t hs[kLdsCells];
-  uint16_t own[kLdsCells];   // cells whose key this round lists (at most one per cell)
-  uint16_t cand[kLdsCells];  // cells that went 2 -> 1 this round (at most once each)
+  int32_t cnt[Cap];
+  uint64_t ks[Cap];
+  uint64_t hs[Cap];
+  uint16_t own[Cap];   // cells whose key this round lists (at most one per cell)
+  uint16_t cand[Cap];  // cells that went 2 -> 1 this round (at most once each)
 };
 
-template <int R>
-__device__ inline bool owns_lds(const Hash &h, const LdsTable &T, uint32_t c, uint32_t *bad) {
+template <int R, typename Table>
+__device__ inline bool owns_lds(const Hash &h, const Table &T, uint32_t c, uint32_t *bad) {
   if (T.cnt[c] != 1) return false;
   const uint64_t ks = T.ks[c];
   const uint64_t hx = check_of(h, ks);
@@ -1787,7 +1793,7 @@ __device__ inline bool owns_lds(const Hash &h, const LdsTable &T, uint32_t c, ui
 template <int R, int NT>
 __device__ void list_table_lds(const iblt_desc desc, iblt_cell *cells, uint32_t N, uint64_t *out,
                                uint64_t out_cap, uint64_t *stats, uint32_t max_rounds,
-                               uint64_t *summary, LdsTable &T) {
+                               uint64_t *summary, LdsTable<kLdsCap<NT>> &T) {
   const Hash h = make_hash_fixed<R>(desc);
   __shared__ uint32_t s_k, s_c, s_bad, s_flags;
   __shared__ unsigned long long s_sum;
@@ -1909,9 +1915,10 @@ struct BatchCtrl {
 };
 
 // first/teams: null when the team schedule is off (a work unit is then a table).
-// LDS words of one batched-listing workgroup.  Registers hold a CU to one
-// 1024-thread, two 512-thread or four 256-thread workgroups (three with the
-// LDS table, 48 KiB); each size takes what leaves that many in 160 KiB.
+// LDS words of one batched-listing workgroup.  A 1024-thread workgroup is
+// alone on its CU by its registers (128 VGPRs), so it takes 128 KiB.  A
+// 512-thread one takes 78 KiB (two fit in a CU's 160 KiB), a 256-thread one
+// 48 KiB with the LDS table (three fit) or 39 KiB without it (four).
 template <int NT, bool LDS>
 constexpr uint32_t kBatchLdsWords = NT == 1024 ? 32768u : NT == 512 ? 19968u : LDS ? 12288u : 9984u;
 
@@ -1923,9 +1930,10 @@ __global__ void __launch_bounds__(NT)
   __shared__ uint32_t s_t;
   // the LDS-resident table, or the in-place schedule's hash set and filter
   __shared__ __align__(16) uint32_t region[kBatchLdsWords<NT, LDS>];
-  static_assert(!LDS || sizeof(LdsTable) <= sizeof(region), "the LDS table fits");
+  using Table = LdsTable<kLdsCap<NT>>;
+  static_assert(!LDS || sizeof(Table) <= sizeof(region), "the LDS table fits");
   static_assert(kBatchLdsWords<NT, LDS> >= kApplySet<NT> + 1024, "the filter has room");
-  LdsTable &lt = *reinterpret_cast<LdsTable *>(region);
+  Table &lt = *reinterpret_cast<Table *>(region);
   uint32_t *hset = region;
   uint32_t *filt = region + kApplySet<NT>;
   constexpr uint32_t filt_words = kBatchLdsWords<NT, LDS> - kApplySet<NT>;
@@ -1987,7 +1995,7 @@ __global__ void __launch_bounds__(NT)
       continue;
     }
     if constexpr (LDS) {
-      if (N <= lds_max) {
+      if (N <= lds_max && N <= kLdsCap<NT>) {
 #define PEEL_LDS_CASE(RR) \
   case RR: list_table_lds<RR, NT>(e.desc, e.cells, N, e.out_keys, e.out_cap, e.round_stats, max_rounds, e.summary, lt); break;
         switch (e.desc.r) {

@@ -75,7 +75,8 @@ def _specs(n, seed, lo=6, hi=14, rs=(2, 3, 4, 5)):
 @pytest.mark.parametrize("lds", [0, pk.IBLT_LDS_MAX_CELLS])
 @pytest.mark.parametrize("threads", [256, 512, 1024])
 def test_batched_matches_oracle(threads, lds):
-    # tables of 2^6 .. 2^14 cells: with lds on, those of <= 2048 cells are listed in LDS
+    # tables of 2^6 .. 2^14 cells: with lds on, those the workgroup size holds
+    # (pk.IBLT_LDS_CELLS) are listed in LDS, the larger ones in place
     need_gpu()
     specs = _specs(48, 3)
     specs.sort(key=lambda x: -x[0])
@@ -112,12 +113,13 @@ def test_in_place_filter_folds(threads):
         _check_against_oracle(t, k, 256)
 
 
-@pytest.mark.parametrize("threads", [256, 1024])
+@pytest.mark.parametrize("threads", [256, 512, 1024])
 def test_lds_schedule_edges(threads):
-    # LDS-resident tables at the size limit and around it, above threshold (a core
-    # remains), a tiny round limit, a tiny output capacity and a corrupt cell.
+    # LDS-resident tables at the size limit of the workgroup size and around it,
+    # above threshold (a core remains), a tiny round limit, a tiny output capacity
+    # and a corrupt cell.
     need_gpu()
-    L = pk.IBLT_LDS_MAX_CELLS
+    L = pk.IBLT_LDS_CELLS[threads]
     specs = [(L, 3, int(0.80 * L), 11), (L, 4, int(0.90 * L), 12), (L + 1, 3, int(0.7 * L), 13),
              (L - 1, 5, int(0.6 * L), 14), (L, 2, int(0.45 * L), 15), (777, 3, 600, 16),
              (3, 3, 1, 17), (4, 4, 0, 18), (L, 3, int(0.75 * L), 19), (L, 3, int(0.7 * L), 20)]
@@ -501,7 +503,8 @@ def test_autotuner_per_class_schedule_is_exact():
     need_gpu()
     from paper_1302_7014_amd.autotune import LARGE_MIN, tune_batched
     specs = _specs(20, 13, lo=8, hi=12, rs=(3,)) + [
-        (LARGE_MIN + 1000 * i, 3, int(0.7 * 0.818 * LARGE_MIN), 900 + i) for i in range(3)]
+        (LARGE_MIN + 1000 * i, 3, int(0.7 * 0.818 * LARGE_MIN), 900 + i) for i in range(3)] + [
+        (N, 3, int(0.7 * 0.818 * N), 950 + i) for i, N in enumerate((8000, 12000, 30000))]
     specs.sort(key=lambda x: -x[0])
     tables, keys, pristine = _make_tables(specs, 128)
     ent = pk.batch_entries(tables, "cuda")
